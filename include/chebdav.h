@@ -1,0 +1,227 @@
+/*
+ * chebdav.h -- block Chebyshev-Davidson for the k smallest eigenpairs of the
+ * normalized graph Laplacian A = I - D^{-1/2} S D^{-1/2} (Pang & Yang,
+ * "A Distributed Block Chebyshev-Davidson Algorithm for Parallel Spectral
+ * Clustering", arXiv 2212.04443), on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns a chebdav_status; 0 is success, negative values
+ *     are errors.  Nothing throws or aborts.  chebdav_last_error() returns a
+ *     message for the calling thread's most recent error.
+ *   - Dense blocks are ROW-MAJOR: element (i, j) of an n x w block with leading
+ *     dimension ld lives at p[i * ld + j]; ld >= w.
+ *   - Pointers documented as "device" must be device memory on the current HIP
+ *     device; the caller owns every buffer it passes (inputs, outputs,
+ *     workspaces) and keeps it alive until the stream work completes.
+ *   - hip_stream is a hipStream_t (NULL = the legacy default stream).  All work
+ *     is enqueued on it in order.  Functions that must read a result back (the
+ *     graph build, orthonormalize, solve) synchronize that stream before they
+ *     return; chebdav_spmm and chebdav_filter do not.
+ *   - On error the contents of output buffers are unspecified; nothing leaks.
+ */
+#ifndef CHEBDAV_H
+#define CHEBDAV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CHEBDAV_OK = 0,
+    CHEBDAV_EINVAL = -1,       /* invalid argument (sizes, ids, interval, NaN input, ...) */
+    CHEBDAV_ENOMEM = -2,       /* device allocation failed or workspace too small */
+    CHEBDAV_EHIP = -3,         /* a HIP runtime call failed */
+    CHEBDAV_ENOCONV = -4,      /* itmax reached: partial results are returned */
+    CHEBDAV_EBREAKDOWN = -5,   /* no independent vector found after repeated replacement */
+    CHEBDAV_EUNSUPPORTED = -6  /* a size beyond the library's limits */
+} chebdav_status;
+
+typedef enum { CHEBDAV_F64 = 0, CHEBDAV_F32 = 1 } chebdav_dtype;
+
+/* Opaque handle owning the device CSR pattern of S and its degree scaling. */
+typedef struct chebdav_graph chebdav_graph;
+
+/* ------------------------------------------------------------------------
+ * Graph -> Laplacian (Eq. 1).
+ *
+ * Builds the canonical symmetric CSR of the simple graph: self-loops are
+ * dropped, repeated edges (either orientation) merged, columns ascending in
+ * each row.  deg_i = row length; dinv_i = 1/sqrt(deg_i) with IEEE
+ * round-to-nearest sqrt and division, 0 for an isolated node (whose row of A is
+ * the identity row, eigenvalue 1).  S is binary, so no values are stored.
+ *
+ * edges: n_edges x 2 int64 node ids in [0, n_nodes), 0-based, either
+ * orientation; host memory if edges_on_device == 0, else device memory.
+ * Errors: EINVAL for n_nodes < 1 or > 2^31 - 1, n_edges < 0 or > 2^30, or any
+ * id outside [0, n_nodes) (checked on the device).
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_build_laplacian(const int64_t *edges, int64_t n_edges, int64_t n_nodes,
+                                       int edges_on_device, void *hip_stream,
+                                       chebdav_graph **out);
+
+/* Sizes: n nodes, nnz stored entries (2 x unique undirected edges), isolated
+ * nodes (deg = 0) and the largest degree.  Any output pointer may be NULL. */
+chebdav_status chebdav_graph_info(const chebdav_graph *g, int64_t *n, int64_t *nnz,
+                                  int64_t *n_isolated, int32_t *max_deg);
+
+/* Copies the CSR into caller device buffers: row_ptr int64[n+1], col int32[nnz],
+ * deg int32[n], dinv double[n].  Any pointer may be NULL (skipped). */
+chebdav_status chebdav_graph_export(const chebdav_graph *g, int64_t *row_ptr, int32_t *col,
+                                    int32_t *deg, double *dinv, void *hip_stream);
+
+/* Releases the handle and its device memory; NULL is allowed. */
+void chebdav_graph_free(chebdav_graph *g);
+
+/* ------------------------------------------------------------------------
+ * Fused sparse step (the building block of Alg. 3, Sec. 3.1's SpMM):
+ *
+ *     Y = alpha * (D^{-1/2} S D^{-1/2}) U + beta * U + gamma * Z
+ *
+ * so A U = U - D^{-1/2} S D^{-1/2} U is alpha = -1, beta = 1, gamma = 0.
+ * U, Z, Y: device, n x w, row-major, common leading dimension ld >= w, of the
+ * element type dt.  Z may be NULL when gamma == 0.  Y must not overlap U or Z.
+ * Neighbour sums are taken in ascending column order in the element type (FP32
+ * accumulation for CHEBDAV_F32); results are deterministic.
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_spmm(const chebdav_graph *g, double alpha, double beta, double gamma,
+                            const void *U, const void *Z, void *Y, int64_t ld, int w,
+                            chebdav_dtype dt, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Chebyshev filter (Alg. 3; closed form Eqs. 3-5):
+ *
+ *     Y = p_m(A) X,   p_m(x) = C_m((x - c)/e) / C_m((scale_pt - c)/e),
+ *     c = (cut + upper)/2,  e = (upper - cut)/2,
+ *
+ * evaluated by the scaled three-term recurrence (m sparse steps).  It damps
+ * [cut, upper] to at most 1/|C_m((scale_pt - c)/e)| and keeps |p_m| <= 1 on
+ * [scale_pt, upper] with p_m(scale_pt) = 1.  For the normalized Laplacian
+ * upper = 2 and scale_pt = 0 (Sec. 2).
+ *
+ * X (input) and Y (output): device double, n x kb row-major with leading
+ * dimensions ldx, ldy >= kb; X is not modified and must not overlap Y.
+ * dt = CHEBDAV_F64 runs the recurrence in FP64; CHEBDAV_F32 converts X to FP32,
+ * runs all m steps in FP32 with FP32 accumulation and writes Y in FP64.
+ * workspace: device, at least chebdav_filter_workspace_size() bytes.
+ * Errors: EINVAL unless m >= 1, kb >= 1, scale_pt < cut < upper.
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_filter_workspace_size(const chebdav_graph *g, int kb, chebdav_dtype dt,
+                                             size_t *bytes);
+chebdav_status chebdav_filter(const chebdav_graph *g, const double *X, int64_t ldx, double *Y,
+                              int64_t ldy, int kb, int m, double cut, double upper,
+                              double scale_pt, chebdav_dtype dt, void *workspace,
+                              size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Block orthonormalization (Alg. 2 step 6): on return X (n x kb, device double,
+ * row-major, ldx) has orthonormal columns, orthogonal to the ksub orthonormal
+ * columns of V (n x ksub, device double, row-major, ldv; may be NULL if
+ * ksub == 0), and spans the same space as (I - V V^T) X_in when that has full
+ * numerical rank.  Method: two block classical Gram-Schmidt passes against V,
+ * then Cholesky QR with a dependence test, then a third pass and a second
+ * Cholesky QR.  A column whose norm after projection is below 1e-10 of its
+ * norm before, or whose pivot in the scaled Gram matrix is below 1e-13, is
+ * numerically dependent and replaced by a Philox4x32-10 column (key = seed,
+ * counters numbered from first_random_col), then everything is redone.
+ * n_replaced (host, may be NULL) receives the number of replacements.
+ * Errors: EBREAKDOWN if dependence persists after 3 rounds of replacement.
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, size_t *bytes);
+chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, double *X,
+                                      int64_t ldx, int kb, int64_t n, uint64_t seed,
+                                      uint64_t first_random_col, int *n_replaced,
+                                      void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Solver (Alg. 2: block Chebyshev-Davidson with inner-outer restart and
+ * progressive filtering of initial vectors).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int k_want;             /* number of smallest eigenpairs wanted (>= 1)                */
+    int kb;                 /* block size: vectors filtered and added per iteration       */
+    int m;                  /* Chebyshev filter degree                                    */
+    int itmax;              /* iteration cap; 0 -> 1000                                   */
+    double tol;             /* converged iff ||A v - theta v||_2 <= tol (||v|| = 1); 0 -> 1e-8 */
+    int act_max;            /* 0 -> max(5 kb, 30)                  (Sec. 4)                */
+    int dim_max;            /* 0 -> max(act_max + 2 kb, k_want + 30)    (Sec. 4)           */
+    int k_ri;               /* inner-restart size; 0 -> max(floor(act_max/2), act_max - 3 kb) */
+    double upperb;          /* spectrum upper bound; 0 -> 2                                */
+    double lowb;            /* spectrum lower bound (filter scale point), normally 0       */
+    double low_nwb0;        /* first cut; NaN or <= lowb -> lowb + (upperb - lowb) k_want / n */
+    chebdav_dtype filter_dtype;  /* F64, or F32 for the mixed-precision form              */
+    double f32_switch_tol;  /* F32 form: the filter runs in FP64 once the smallest residual
+                               among the non-converged leading pairs falls below this
+                               (0 -> 1e-5); every other step is always FP64               */
+    uint64_t seed;          /* Philox key for all random vectors                           */
+    int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
+} chebdav_params;
+
+typedef struct {
+    int iterations;         /* Davidson iterations run                                    */
+    int converged;          /* locked eigenpairs (>= k_want on success)                  */
+    int n_spmm_filter;      /* sparse steps spent in filters                              */
+    int n_spmm_filter_f32;  /* ... of which in FP32                                       */
+    int n_spmm_other;       /* other sparse products (W = A V and the exit certificate)   */
+    int n_random;           /* random (Philox) columns drawn                              */
+    int n_replaced;         /* of which replacements of dependent vectors                 */
+    double max_residual;    /* max_i ||A v_i - lambda_i v_i||_2 of the returned pairs,
+                               from a fresh sparse product after convergence              */
+    double t_total_ms;      /* wall time of the call                                       */
+    double t_filter_ms;     /* with timing != 0: event-timed filter time (else 0)          */
+    int n_filter_launches;  /* with timing != 0: filter step launches timed                */
+} chebdav_stats;
+
+/* Device bytes needed by chebdav_solve for this graph and these parameters. */
+chebdav_status chebdav_solve_workspace_size(const chebdav_graph *g, const chebdav_params *p,
+                                            size_t *bytes);
+
+/* Finds the k_want smallest eigenpairs of A.
+ * V_init: device double, n x k_init row-major (ld = k_init), may be NULL; its
+ *   columns are used in the given order and should be sorted by non-decreasing
+ *   Rayleigh quotient (progressive filtering, Sec. 2).  NaN/Inf -> EINVAL.
+ * evals: device double[k_want], ascending.
+ * evecs: device double, n x k_want row-major (ld = k_want), orthonormal columns.
+ * stats: host, may be NULL.
+ * Errors: EINVAL for invalid parameters (including dim_max < k_want + 2 kb + 1,
+ * k_ri > act_max - kb, dim_max > n); ENOCONV when itmax is reached (the
+ * converged pairs are still written; stats->converged tells how many). */
+chebdav_status chebdav_solve(const chebdav_graph *g, const chebdav_params *p,
+                             const double *V_init, int k_init, double *evals, double *evecs,
+                             chebdav_stats *stats, void *workspace, size_t ws_bytes,
+                             void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Building blocks exposed for verification.
+ * ------------------------------------------------------------------------ */
+/* Symmetric eigendecomposition of the n x n matrix H (device double, row-major,
+ * ldh; only read): evals ascending (device double[n]); evecs (device double,
+ * n x n, row-major, ldy) with orthonormal columns, column j for evals[j].
+ * Method: Householder tridiagonalization, bisection, inverse iteration with
+ * reorthogonalization inside clusters, back-transformation.  1 <= n <= 1024. */
+chebdav_status chebdav_small_eig_workspace_size(int n, size_t *bytes);
+chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *evals, double *evecs,
+                                 int64_t ldy, void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* Fills X(:, j), j < w (device double, n x w, row-major, ld), with Philox4x32-10
+ * uniforms on [-1, 1): entry (r, j) uses counter (r mod 2^32, r >> 32,
+ * first_col + j, 0) and key (seed mod 2^32, seed >> 32); value =
+ * ((w1 << 32 | w0) >> 11) * 2^-52 - 1 for the first two output words. */
+chebdav_status chebdav_philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
+                                   uint64_t first_col, void *hip_stream);
+
+/* dinv[i] = 1/sqrt(deg[i]) (0 for deg[i] <= 0) with the device arithmetic the
+ * Laplacian build uses: IEEE round-to-nearest sqrt of the degree as a double,
+ * then a round-to-nearest division.  deg, dinv: device arrays of n entries. */
+chebdav_status chebdav_dinv(const int32_t *deg, double *dinv, int64_t n, void *hip_stream);
+
+/* Message for the calling thread's most recent error (never NULL). */
+const char *chebdav_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHEBDAV_H */

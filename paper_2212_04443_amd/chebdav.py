@@ -1,0 +1,303 @@
+"""ctypes binding of libchebdav.so (include/chebdav.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory and the current HIP stream.  Dense blocks are
+row-major torch tensors whose last dimension is contiguous; the leading
+dimension passed to the library is the tensor's row stride.
+
+The library must be built (python -m paper_2212_04443_amd.build); importing
+this module raises if it is missing, and there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchebdav.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+F64, F32 = 0, 1
+_STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "EBREAKDOWN",
+           -6: "EUNSUPPORTED"}
+
+EXPORTED = [
+    "chebdav_build_laplacian", "chebdav_graph_info", "chebdav_graph_export", "chebdav_graph_free",
+    "chebdav_spmm", "chebdav_filter_workspace_size", "chebdav_filter",
+    "chebdav_orthonormalize_workspace_size", "chebdav_orthonormalize",
+    "chebdav_solve_workspace_size", "chebdav_solve", "chebdav_small_eig_workspace_size",
+    "chebdav_small_eig", "chebdav_philox_fill", "chebdav_dinv", "chebdav_last_error",
+]
+
+
+class ChebdavError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (_STATUS.get(status, "?"), status, msg))
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("k_want", ctypes.c_int), ("kb", ctypes.c_int), ("m", ctypes.c_int), ("itmax", ctypes.c_int),
+        ("tol", ctypes.c_double), ("act_max", ctypes.c_int), ("dim_max", ctypes.c_int),
+        ("k_ri", ctypes.c_int), ("upperb", ctypes.c_double), ("lowb", ctypes.c_double),
+        ("low_nwb0", ctypes.c_double), ("filter_dtype", ctypes.c_int),
+        ("f32_switch_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("timing", ctypes.c_int),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("n_spmm_filter", ctypes.c_int),
+        ("n_spmm_filter_f32", ctypes.c_int), ("n_spmm_other", ctypes.c_int),
+        ("n_random", ctypes.c_int), ("n_replaced", ctypes.c_int), ("max_residual", ctypes.c_double),
+        ("t_total_ms", ctypes.c_double), ("t_filter_ms", ctypes.c_double),
+        ("n_filter_launches", ctypes.c_int),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libchebdav.so is not built: run `python -m paper_2212_04443_amd.build`")
+    L = ctypes.CDLL(_LIB_PATH)
+    p, i64, i32, d, u64, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_uint64, ctypes.c_size_t)
+    P = ctypes.POINTER
+    sig = {
+        "chebdav_build_laplacian": [p, i64, i64, i32, p, P(p)],
+        "chebdav_graph_info": [p, P(i64), P(i64), P(i64), P(ctypes.c_int32)],
+        "chebdav_graph_export": [p, p, p, p, p, p],
+        "chebdav_spmm": [p, d, d, d, p, p, p, i64, i32, i32, p],
+        "chebdav_filter_workspace_size": [p, i32, i32, P(sz)],
+        "chebdav_filter": [p, p, i64, p, i64, i32, i32, d, d, d, i32, p, sz, p],
+        "chebdav_orthonormalize_workspace_size": [i64, i32, i32, P(sz)],
+        "chebdav_orthonormalize": [p, i64, i32, p, i64, i32, i64, u64, u64, P(i32), p, sz, p],
+        "chebdav_solve_workspace_size": [p, P(Params), P(sz)],
+        "chebdav_solve": [p, P(Params), p, i32, p, p, P(Stats), p, sz, p],
+        "chebdav_small_eig_workspace_size": [i32, P(sz)],
+        "chebdav_small_eig": [p, i64, i32, p, p, i64, p, sz, p],
+        "chebdav_philox_fill": [p, i64, i32, i64, u64, u64, p],
+        "chebdav_dinv": [p, p, i64, p],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.chebdav_graph_free.argtypes = [p]
+    L.chebdav_graph_free.restype = None
+    L.chebdav_last_error.argtypes = []
+    L.chebdav_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def last_error() -> str:
+    return _lib.chebdav_last_error().decode()
+
+
+def _check(st: int):
+    if st != OK:
+        raise ChebdavError(st, last_error())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _ld(t: torch.Tensor) -> int:
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError("expected a 2-D tensor with contiguous rows")
+    return t.stride(0)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class Graph:
+    """Device CSR of S with its degree scaling; frees itself when collected."""
+
+    def __init__(self, handle: ctypes.c_void_p, device):
+        self._h = handle
+        self.device = device
+        n, nnz, iso, mx = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(_lib.chebdav_graph_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(iso),
+                                       ctypes.byref(mx)))
+        self.n, self.nnz, self.n_isolated, self.max_deg = n.value, nnz.value, iso.value, mx.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            _lib.chebdav_graph_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_laplacian(edges, n_nodes: int, device="cuda", stream=None) -> Graph:
+    """chebdav_build_laplacian from an (E, 2) int64 edge list (NumPy array or
+    torch tensor; a CUDA tensor is read in place)."""
+    if isinstance(edges, torch.Tensor):
+        e = edges.to(torch.int64).contiguous()
+        on_dev = 1 if e.is_cuda else 0
+        if not on_dev:
+            e = e.numpy()
+    else:
+        e = np.ascontiguousarray(np.asarray(edges, dtype=np.int64).reshape(-1, 2))
+        on_dev = 0
+    n_edges = int(e.shape[0]) if e.ndim == 2 else 0
+    ptr = ctypes.c_void_p(e.data_ptr()) if on_dev else ctypes.c_void_p(e.ctypes.data)
+    h = ctypes.c_void_p()
+    with torch.cuda.device(torch.device(device)):
+        _check(_lib.chebdav_build_laplacian(ptr, n_edges, int(n_nodes), on_dev, _stream(stream),
+                                            ctypes.byref(h)))
+    return Graph(h, torch.device(device))
+
+
+def graph_export(g: Graph, stream=None):
+    """Returns (row_ptr int64[n+1], col int32[nnz], deg int32[n], dinv float64[n]) on the device."""
+    dev = g.device
+    rp = torch.empty(g.n + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(max(g.nnz, 1), dtype=torch.int32, device=dev)
+    deg = torch.empty(g.n, dtype=torch.int32, device=dev)
+    dinv = torch.empty(g.n, dtype=torch.float64, device=dev)
+    _check(_lib.chebdav_graph_export(g.handle, _ptr(rp), _ptr(col), _ptr(deg), _ptr(dinv), _stream(stream)))
+    return rp, col[: g.nnz], deg, dinv
+
+
+def spmm(g: Graph, alpha: float, beta: float, gamma: float, U: torch.Tensor, Z, Y: torch.Tensor,
+         stream=None):
+    """Y = alpha D^{-1/2} S D^{-1/2} U + beta U + gamma Z (float64 or float32)."""
+    dt = {torch.float64: F64, torch.float32: F32}[U.dtype]
+    ld = _ld(U)
+    if _ld(Y) != ld or (Z is not None and _ld(Z) != ld):
+        raise ValueError("U, Z and Y must share the leading dimension")
+    _check(_lib.chebdav_spmm(g.handle, alpha, beta, gamma, _ptr(U), _ptr(Z), _ptr(Y), ld,
+                             U.shape[1], dt, _stream(stream)))
+    return Y
+
+
+def filter(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float = 2.0, scale_pt: float = 0.0,
+           dtype: int = F64, Y: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
+           stream=None) -> torch.Tensor:
+    """chebdav_filter: Y = p_m(A) X (X float64, n x kb)."""
+    kb = X.shape[1]
+    if Y is None:
+        Y = torch.empty_like(X)
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_filter_workspace_size(g.handle, kb, dtype, ctypes.byref(nb)))
+    if workspace is None or workspace.numel() < nb.value:
+        workspace = _workspace(nb.value, X.device)
+    _check(_lib.chebdav_filter(g.handle, _ptr(X), _ld(X), _ptr(Y), _ld(Y), kb, m, cut, upper, scale_pt,
+                               dtype, _ptr(workspace), workspace.numel(), _stream(stream)))
+    return Y
+
+
+def orthonormalize(V, X: torch.Tensor, seed: int = 0, first_random_col: int = 0, stream=None) -> int:
+    """chebdav_orthonormalize, in place on X; returns the number of replaced columns."""
+    n, kb = X.shape
+    ksub = 0 if V is None else V.shape[1]
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_orthonormalize_workspace_size(n, ksub, kb, ctypes.byref(nb)))
+    ws = _workspace(nb.value, X.device)
+    rep = ctypes.c_int(0)
+    _check(_lib.chebdav_orthonormalize(_ptr(V) if ksub else ctypes.c_void_p(0), _ld(V) if ksub else 1,
+                                       ksub, _ptr(X), _ld(X), kb, n, seed, first_random_col,
+                                       ctypes.byref(rep), _ptr(ws), ws.numel(), _stream(stream)))
+    return rep.value
+
+
+def make_params(k_want, kb, m, tol=1e-8, itmax=0, act_max=0, dim_max=0, k_ri=0, upperb=2.0,
+                lowb=0.0, low_nwb0=math.nan, filter_dtype=F64, f32_switch_tol=0.0, seed=0,
+                timing=False) -> Params:
+    return Params(k_want, kb, m, itmax, tol, act_max, dim_max, k_ri, upperb, lowb, low_nwb0,
+                  filter_dtype, f32_switch_tol, seed, 1 if timing else 0)
+
+
+def solve_workspace_size(g: Graph, params: Params) -> int:
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_solve_workspace_size(g.handle, ctypes.byref(params), ctypes.byref(nb)))
+    return nb.value
+
+
+@dataclass
+class SolveResult:
+    evals: torch.Tensor
+    evecs: torch.Tensor
+    stats: dict
+    status: int
+
+
+def solve(g: Graph, params: Params, V_init: torch.Tensor | None = None,
+          workspace: torch.Tensor | None = None, stream=None, allow_noconv: bool = False) -> SolveResult:
+    """chebdav_solve.  Returns evals (k_want,), evecs (n, k_want) and the stats."""
+    need = solve_workspace_size(g, params)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, g.device)
+    evals = torch.empty(params.k_want, dtype=torch.float64, device=g.device)
+    evecs = torch.empty(g.n, params.k_want, dtype=torch.float64, device=g.device)
+    st = Stats()
+    k_init = 0
+    vptr = ctypes.c_void_p(0)
+    if V_init is not None:
+        if not V_init.is_contiguous() or V_init.dtype != torch.float64:
+            raise ValueError("V_init must be a contiguous float64 (n, k_init) tensor")
+        k_init = V_init.shape[1]
+        vptr = _ptr(V_init)
+    rc = _lib.chebdav_solve(g.handle, ctypes.byref(params), vptr, k_init, _ptr(evals), _ptr(evecs),
+                            ctypes.byref(st), _ptr(workspace), workspace.numel(), _stream(stream))
+    if rc != OK and not (allow_noconv and rc == ENOCONV):
+        raise ChebdavError(rc, last_error())
+    return SolveResult(evals, evecs, st.as_dict(), rc)
+
+
+def small_eig(H: torch.Tensor, stream=None):
+    """chebdav_small_eig: (ascending eigenvalues, eigenvectors as columns)."""
+    n = H.shape[0]
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_small_eig_workspace_size(n, ctypes.byref(nb)))
+    ws = _workspace(nb.value, H.device)
+    w = torch.empty(n, dtype=torch.float64, device=H.device)
+    Y = torch.empty(n, n, dtype=torch.float64, device=H.device)
+    _check(_lib.chebdav_small_eig(_ptr(H), _ld(H), n, _ptr(w), _ptr(Y), _ld(Y), _ptr(ws), ws.numel(),
+                                  _stream(stream)))
+    return w, Y
+
+
+def philox_fill(n: int, w: int, seed: int, first_col: int = 0, device="cuda", stream=None):
+    X = torch.empty(n, w, dtype=torch.float64, device=device)
+    _check(_lib.chebdav_philox_fill(_ptr(X), n, w, w, seed, first_col, _stream(stream)))
+    return X
+
+
+def dinv(deg: torch.Tensor, stream=None) -> torch.Tensor:
+    """chebdav_dinv on an int32 device tensor."""
+    out = torch.empty(deg.shape[0], dtype=torch.float64, device=deg.device)
+    _check(_lib.chebdav_dinv(_ptr(deg), _ptr(out), deg.shape[0], _stream(stream)))
+    return out

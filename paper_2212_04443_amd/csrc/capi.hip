@@ -1,0 +1,217 @@
+// The C ABI (include/chebdav.h): argument checks, error reporting, dispatch.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "internal.h"
+
+struct chebdav_graph {
+    chebdav::Graph *g;
+};
+
+namespace chebdav {
+
+namespace {
+thread_local std::string g_last_error = "no error";
+
+struct PinnedSlot {
+    void *p = nullptr;
+    size_t cap = 0;
+    ~PinnedSlot() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+thread_local PinnedSlot g_pinned[4];
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error = "no error"; }
+
+chebdav_status fail(chebdav_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+void *pinned_host(size_t bytes, int slot) {
+    PinnedSlot &s = g_pinned[slot];
+    if (s.cap < bytes) {
+        if (s.p) (void)hipHostFree(s.p);
+        s.p = nullptr;
+        s.cap = 0;
+        const size_t want = std::max<size_t>(bytes, 4096);
+        if (hipHostMalloc(&s.p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+        s.cap = want;
+    }
+    return s.p;
+}
+
+chebdav_status solve_workspace_size(const Graph *g, const chebdav_params *p, size_t *bytes);
+chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_init, int k_init,
+                     double *evals, double *evecs, chebdav_stats *stats, void *ws, size_t ws_bytes,
+                     hipStream_t st);
+
+}  // namespace chebdav
+
+using namespace chebdav;
+
+#define CHECK_GRAPH(gh)                                                 \
+    do {                                                                \
+        if (!(gh) || !(gh)->g) return fail(CHEBDAV_EINVAL, "graph is NULL"); \
+    } while (0)
+
+extern "C" {
+
+chebdav_status chebdav_build_laplacian(const int64_t *edges, int64_t n_edges, int64_t n_nodes,
+                                       int edges_on_device, void *hip_stream, chebdav_graph **out) {
+    if (!out) return fail(CHEBDAV_EINVAL, "out is NULL");
+    *out = nullptr;
+    Graph *g = nullptr;
+    CD_TRY(build_graph(edges, n_edges, n_nodes, edges_on_device, as_stream(hip_stream), &g));
+    *out = new chebdav_graph{g};
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_graph_info(const chebdav_graph *gh, int64_t *n, int64_t *nnz,
+                                  int64_t *n_isolated, int32_t *max_deg) {
+    CHECK_GRAPH(gh);
+    if (n) *n = gh->g->n;
+    if (nnz) *nnz = gh->g->nnz;
+    if (n_isolated) *n_isolated = gh->g->n_isolated;
+    if (max_deg) *max_deg = gh->g->max_deg;
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_graph_export(const chebdav_graph *gh, int64_t *row_ptr, int32_t *col,
+                                    int32_t *deg, double *dinv, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    const Graph *g = gh->g;
+    hipStream_t st = as_stream(hip_stream);
+    if (row_ptr) CD_HIP(hipMemcpyAsync(row_ptr, g->row_ptr, sizeof(int64_t) * (g->n + 1), hipMemcpyDeviceToDevice, st));
+    if (col && g->nnz) CD_HIP(hipMemcpyAsync(col, g->col, sizeof(int32_t) * g->nnz, hipMemcpyDeviceToDevice, st));
+    if (deg) CD_HIP(hipMemcpyAsync(deg, g->deg, sizeof(int32_t) * g->n, hipMemcpyDeviceToDevice, st));
+    if (dinv) CD_HIP(hipMemcpyAsync(dinv, g->dinv, sizeof(double) * g->n, hipMemcpyDeviceToDevice, st));
+    return CHEBDAV_OK;
+}
+
+void chebdav_graph_free(chebdav_graph *gh) {
+    if (!gh) return;
+    free_graph(gh->g);
+    delete gh;
+}
+
+chebdav_status chebdav_spmm(const chebdav_graph *gh, double alpha, double beta, double gamma,
+                            const void *U, const void *Z, void *Y, int64_t ld, int w,
+                            chebdav_dtype dt, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (U == Y || (Z && Z == Y)) return fail(CHEBDAV_EINVAL, "Y must not overlap U or Z");
+    hipStream_t st = as_stream(hip_stream);
+    if (dt == CHEBDAV_F64)
+        return launch_cheb_step<double, double>(gh->g, alpha, beta, gamma, static_cast<const double *>(U), ld,
+                                                static_cast<const double *>(Z), ld, static_cast<double *>(Y), ld, w,
+                                                st);
+    if (dt == CHEBDAV_F32)
+        return launch_cheb_step<float, float>(gh->g, alpha, beta, gamma, static_cast<const float *>(U), ld,
+                                              static_cast<const float *>(Z), ld, static_cast<float *>(Y), ld, w, st);
+    return fail(CHEBDAV_EINVAL, "bad dtype");
+}
+
+chebdav_status chebdav_filter_workspace_size(const chebdav_graph *gh, int kb, chebdav_dtype dt,
+                                             size_t *bytes) {
+    CHECK_GRAPH(gh);
+    if (!bytes || kb < 1) return fail(CHEBDAV_EINVAL, "bad arguments");
+    if (dt != CHEBDAV_F64 && dt != CHEBDAV_F32) return fail(CHEBDAV_EINVAL, "bad dtype");
+    *bytes = filter_ws_bytes(gh->g->n, kb, dt);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_filter(const chebdav_graph *gh, const double *X, int64_t ldx, double *Y,
+                              int64_t ldy, int kb, int m, double cut, double upper,
+                              double scale_pt, chebdav_dtype dt, void *workspace,
+                              size_t ws_bytes, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!X || !Y) return fail(CHEBDAV_EINVAL, "NULL block");
+    if (X == Y) return fail(CHEBDAV_EINVAL, "X and Y must not overlap");
+    return run_filter(gh->g, X, ldx, Y, ldy, kb, m, cut, upper, scale_pt, dt, workspace, ws_bytes,
+                      as_stream(hip_stream), nullptr, nullptr);
+}
+
+chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, size_t *bytes) {
+    if (!bytes || n < 1 || ksub < 0 || kb < 1) return fail(CHEBDAV_EINVAL, "bad arguments");
+    *bytes = orth_ws_bytes(n, ksub, kb);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, double *X,
+                                      int64_t ldx, int kb, int64_t n, uint64_t seed,
+                                      uint64_t first_random_col, int *n_replaced,
+                                      void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!X || n < 1 || kb < 1 || ksub < 0 || ldx < kb) return fail(CHEBDAV_EINVAL, "bad arguments");
+    if (ksub > 0 && (!V || ldv < ksub)) return fail(CHEBDAV_EINVAL, "bad basis V");
+    Seg2 v;
+    v.X1 = V;
+    v.ld1 = ldv;
+    v.p1 = ksub;
+    uint64_t next = first_random_col;
+    int rep = 0;
+    hipStream_t st = as_stream(hip_stream);
+    CD_TRY(orthonormalize(v, X, ldx, kb, n, seed, &next, &rep, workspace, ws_bytes, st));
+    CD_HIP(hipStreamSynchronize(st));
+    if (n_replaced) *n_replaced = rep;
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_solve_workspace_size(const chebdav_graph *gh, const chebdav_params *p,
+                                            size_t *bytes) {
+    CHECK_GRAPH(gh);
+    if (!bytes) return fail(CHEBDAV_EINVAL, "bytes is NULL");
+    return solve_workspace_size(gh->g, p, bytes);
+}
+
+chebdav_status chebdav_solve(const chebdav_graph *gh, const chebdav_params *p,
+                             const double *V_init, int k_init, double *evals, double *evecs,
+                             chebdav_stats *stats, void *workspace, size_t ws_bytes,
+                             void *hip_stream) {
+    CHECK_GRAPH(gh);
+    return solve(gh->g, p, V_init, k_init, evals, evecs, stats, workspace, ws_bytes, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_small_eig_workspace_size(int n, size_t *bytes) {
+    if (!bytes || n < 1 || n > 1024) return fail(CHEBDAV_EINVAL, "n must be in [1, 1024]");
+    *bytes = eig_ws_bytes(n);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *evals, double *evecs,
+                                 int64_t ldy, void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!H || !evals || !evecs) return fail(CHEBDAV_EINVAL, "NULL argument");
+    return small_eig(H, ldh, n, evals, evecs, ldy, workspace, ws_bytes, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
+                                   uint64_t first_col, void *hip_stream) {
+    if (!X || n < 0 || w < 0 || ld < w) return fail(CHEBDAV_EINVAL, "bad arguments");
+    return philox_fill(X, n, w, ld, seed, first_col, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_dinv(const int32_t *deg, double *dinv, int64_t n, void *hip_stream) {
+    if (n < 0 || (n > 0 && (!deg || !dinv))) return fail(CHEBDAV_EINVAL, "bad arguments");
+    return dinv_table(deg, dinv, n, as_stream(hip_stream));
+}
+
+const char *chebdav_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

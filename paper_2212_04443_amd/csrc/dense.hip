@@ -1,0 +1,392 @@
+// Dense FP64 kernels on tall row-major blocks (n rows, few columns):
+//   gram     C = Xs^T Y      (Rayleigh-quotient columns, Gram matrices)
+//   update   Y = a Xs B + b Y (projections, Cholesky-QR, subspace rotation)
+//   colnorms ||X(:,j) - Y(:,j) theta_j||_2 (residuals, column norms)
+//   gather_cols / copy_block / fill / philox_fill / check_finite
+// Xs is a "two-segment" column range: the locked and active parts of the basis
+// are separate arrays, so V(:, 1:ksub) = [Vlocked, Vactive] is read in place.
+// Reductions over n are split over row ranges, written to a partial buffer and
+// summed in a fixed order, so every result is deterministic.
+#include <algorithm>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace chebdav {
+namespace {
+
+constexpr int TB = 64;   // tile edge (rows / columns of the output tile)
+constexpr int KC = 16;   // reduction chunk
+constexpr int NT = 256;  // threads per block (16 x 16, each a 4 x 4 sub-tile)
+
+__device__ inline double seg_load(const Seg2 &s, int64_t row, int c) {
+    return c < s.p1 ? s.X1[row * s.ld1 + c] : s.X2[row * s.ld2 + (c - s.p1)];
+}
+
+// Partial Gram: part[z][i][j] = sum over rows of split z of Xs[row][i] Y[row][j].
+__global__ void __launch_bounds__(NT) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy,
+                                             int q, int64_t n, int64_t rows_per_split,
+                                             double *__restrict__ part) {
+    __shared__ double sa[KC][TB + 1];
+    __shared__ double sb[KC][TB + 1];
+    const int p = xs.cols();
+    const int i0 = blockIdx.x * TB, j0 = blockIdx.y * TB;
+    const int64_t r_beg = (int64_t)blockIdx.z * rows_per_split;
+    const int64_t r_end = min(n, r_beg + rows_per_split);
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int64_t r0 = r_beg; r0 < r_end; r0 += KC) {
+#pragma unroll
+        for (int t = 0; t < (KC * TB) / NT; ++t) {
+            const int e = threadIdx.x + t * NT;
+            const int kk = e / TB, c = e % TB;
+            const int64_t row = r0 + kk;
+            const bool rv = row < r_end;
+            sa[kk][c] = (rv && i0 + c < p) ? seg_load(xs, row, i0 + c) : 0.0;
+            sb[kk][c] = (rv && j0 + c < q) ? Y[row * ldy + j0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = sa[kk][ty * 4 + u];
+                b[u] = sb[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+    double *out = part + (int64_t)blockIdx.z * p * q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
+            if (i < p && j < q) out[(int64_t)i * q + j] = acc[u][v];
+        }
+}
+
+__global__ void k_gram_reduce(const double *__restrict__ part, int splits, int p, int q,
+                              double *__restrict__ C, int64_t ldc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)p * q) return;
+    double s = 0.0;
+    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * p * q + e];
+    C[(e / q) * ldc + (e % q)] = s;
+}
+
+int gram_splits(int64_t n, int p, int q) {
+    const int tiles = (int)(ceil_div(p, TB) * ceil_div(q, TB));
+    int64_t s = std::max<int64_t>(1, 1024 / tiles);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n, 256)));
+    return (int)s;
+}
+
+// Y = alpha Xs B + beta Y; one block owns a 64-row x 64-column tile of Y and
+// writes it only after it has read every row of Xs it needs.
+__global__ void __launch_bounds__(NT) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
+                                               double alpha, double beta, double *Y, int64_t ldy,
+                                               int q, int64_t n) {
+    __shared__ double sx[TB][KC + 1];
+    __shared__ double sb[KC][TB + 1];
+    const int p = xs.cols();
+    const int64_t r0 = (int64_t)blockIdx.x * TB;
+    const int j0 = blockIdx.y * TB;
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    double acc[4][4] = {};
+    for (int k0 = 0; k0 < p; k0 += KC) {
+#pragma unroll
+        for (int t = 0; t < (KC * TB) / NT; ++t) {
+            const int e = threadIdx.x + t * NT;
+            {  // X tile: 64 rows x 16 columns
+                const int rr = e / KC, kk = e % KC;
+                const int64_t row = r0 + rr;
+                sx[rr][kk] = (row < n && k0 + kk < p) ? seg_load(xs, row, k0 + kk) : 0.0;
+            }
+            {  // B tile: 16 rows x 64 columns
+                const int kk = e / TB, c = e % TB;
+                sb[kk][c] = (k0 + kk < p && j0 + c < q) ? B[(int64_t)(k0 + kk) * ldb + j0 + c] : 0.0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KC; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = sx[ty * 4 + u][kk];
+                b[u] = sb[kk][tx * 4 + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int64_t row = r0 + ty * 4 + u;
+        if (row >= n) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int j = j0 + tx * 4 + v;
+            if (j >= q) continue;
+            double *y = Y + row * ldy + j;
+            *y = beta == 0.0 ? alpha * acc[u][v] : alpha * acc[u][v] + beta * (*y);
+        }
+    }
+}
+
+// Column sums of squares of (X - Y diag(theta)) over a row range per block.
+__global__ void __launch_bounds__(NT) k_colnorm(const double *__restrict__ X, int64_t ldx,
+                                                const double *__restrict__ Y, int64_t ldy,
+                                                const double *__restrict__ theta, int w, int64_t n,
+                                                int64_t rows_per_block, double *__restrict__ part) {
+    __shared__ double red[NT];
+    const int R = NT / w;  // row lanes (w <= NT)
+    const int c = threadIdx.x % w, rr = threadIdx.x / w;
+    const int64_t r_beg = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r_end = min(n, r_beg + rows_per_block);
+    double s = 0.0;
+    if (rr < R) {
+        const double th = (Y && theta) ? theta[c] : 0.0;
+        for (int64_t r = r_beg + rr; r < r_end; r += R) {
+            double v = X[r * ldx + c];
+            if (Y) v -= Y[r * ldy + c] * th;
+            s += v * v;
+        }
+    }
+    red[threadIdx.x] = (rr < R) ? s : 0.0;
+    __syncthreads();
+    if (threadIdx.x < w) {
+        double t = 0.0;
+        for (int k = 0; k < R; ++k) t += red[k * w + threadIdx.x];
+        part[(int64_t)blockIdx.x * w + threadIdx.x] = t;
+    }
+}
+
+__global__ void k_colnorm_reduce(const double *__restrict__ part, int blocks, int w,
+                                 double *__restrict__ out) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= w) return;
+    double s = 0.0;
+    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * w + j];
+    out[j] = sqrt(s);
+}
+
+constexpr int kColnormBlocks = 512;
+
+// One wavefront per row: stage the row's selected entries, then write them.
+template <int PER_LANE>
+__global__ void k_gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
+                              const int32_t *__restrict__ map, int w, int64_t n) {
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    if (r >= n) return;
+    const int lane = lane_id();
+    double v[PER_LANE];
+#pragma unroll
+    for (int t = 0; t < PER_LANE; ++t) {
+        const int j = lane + t * kWave;
+        v[t] = j < w ? Src[r * lds + map[j]] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < PER_LANE; ++t) {
+        const int j = lane + t * kWave;
+        if (j < w) Dst[r * ldd + j] = v[t];
+    }
+}
+
+template <typename TS, typename TD>
+__global__ void k_copy_block(const TS *__restrict__ S, int64_t lds, TD *__restrict__ D, int64_t ldd,
+                             int w, int64_t n) {
+    const int64_t total = n * (int64_t)w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t r = e / w;
+        const int c = (int)(e - r * w);
+        D[r * ldd + c] = (TD)S[r * lds + c];
+    }
+}
+
+__global__ void k_fill(double *__restrict__ p, int64_t count, double v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) p[e] = v;
+}
+
+// Philox4x32-10 (Salmon et al. 2011).
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)M0 * c[0];
+        const uint64_t p1 = (uint64_t)M1 * c[2];
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+__global__ void k_philox(double *__restrict__ X, int64_t n, int w, int64_t ld, uint64_t seed,
+                         uint64_t first_col) {
+    const int64_t total = n * (int64_t)w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t r = e / w;
+        const int j = (int)(e - r * w);
+        const uint64_t q = first_col + (uint64_t)j;
+        uint32_t c[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32), (uint32_t)q, 0u};
+        philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const uint64_t u = (((uint64_t)c[1] << 32) | c[0]) >> 11;
+        X[r * ld + j] = (double)u * 0x1.0p-52 - 1.0;
+    }
+}
+
+__global__ void k_check_finite(const double *__restrict__ X, int64_t ld, int w, int64_t n,
+                               int *__restrict__ flag) {
+    const int64_t total = n * (int64_t)w;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int bad = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int64_t r = e / w;
+        const int c = (int)(e - r * w);
+        bad |= !isfinite(X[r * ld + c]);
+    }
+    if (__any(bad) && lane_id() == 0) atomicOr(flag, 1);
+}
+
+unsigned grid_for(int64_t total) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(total, 256), 8192));
+}
+
+}  // namespace
+
+// Upper bound of splits * p' * q' over all p' <= p, q' <= q: splits * tiles <=
+// max(tiles, 1024) and p' q' <= tiles * TB * TB.
+size_t gram_partial_elems(int64_t, int p, int q) {
+    const int64_t tiles = ceil_div(std::max(p, 1), TB) * ceil_div(std::max(q, 1), TB);
+    return (size_t)std::max<int64_t>(tiles, 1024) * TB * TB;
+}
+
+chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t n, double *C,
+                    int64_t ldc, double *partial, hipStream_t st) {
+    const int p = Xs.cols();
+    if (p == 0 || q == 0) return CHEBDAV_OK;
+    const int splits = gram_splits(n, p, q);
+    const int64_t rps = ceil_div(ceil_div(n, splits), KC) * KC;
+    const dim3 grid((unsigned)ceil_div(p, TB), (unsigned)ceil_div(q, TB), (unsigned)splits);
+    hipLaunchKernelGGL(k_gram, grid, dim3(NT), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    CD_LAUNCH_CHECK();
+    const int64_t pq = (int64_t)p * q;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(pq, 256)), dim3(256), 0, st, partial,
+                       splits, p, q, C, ldc);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+int update_max_inplace_cols() { return TB; }
+
+chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha, double beta,
+                      double *Y, int64_t ldy, int q, int64_t n, hipStream_t st) {
+    if (q == 0 || n == 0) return CHEBDAV_OK;
+    if (Xs.cols() == 0) {
+        if (beta == 1.0) return CHEBDAV_OK;
+        return fail(CHEBDAV_EUNSUPPORTED, "update with an empty basis");
+    }
+    const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, TB));
+    hipLaunchKernelGGL(k_update, grid, dim3(NT), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+size_t colnorm_partial_elems(int64_t, int w) { return (size_t)kColnormBlocks * std::max(w, 1); }
+
+chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                        const double *theta, int w, int64_t n, double *out, double *partial,
+                        hipStream_t st) {
+    if (w == 0) return CHEBDAV_OK;
+    for (int c0 = 0; c0 < w; c0 += NT) {
+        const int pw = std::min(NT, w - c0);
+        const int blocks = (int)std::min<int64_t>(kColnormBlocks, std::max<int64_t>(1, ceil_div(n, 64)));
+        const int64_t rpb = ceil_div(n, blocks);
+        hipLaunchKernelGGL(k_colnorm, dim3(blocks), dim3(NT), 0, st, X + c0, ldx, Y ? Y + c0 : nullptr,
+                           ldy, theta ? theta + c0 : nullptr, pw, n, rpb, partial);
+        CD_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_colnorm_reduce, dim3((unsigned)ceil_div(pw, 256)), dim3(256), 0, st,
+                           partial, blocks, pw, out + c0);
+        CD_LAUNCH_CHECK();
+    }
+    return CHEBDAV_OK;
+}
+
+chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
+                           const int32_t *map, int w, int64_t n, hipStream_t st) {
+    if (w == 0 || n == 0) return CHEBDAV_OK;
+    const unsigned grid = (unsigned)ceil_div(n, 4);
+    if (w <= 64)
+        hipLaunchKernelGGL(k_gather_cols<1>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+    else if (w <= 128)
+        hipLaunchKernelGGL(k_gather_cols<2>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+    else if (w <= 256)
+        hipLaunchKernelGGL(k_gather_cols<4>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+    else if (w <= 512)
+        hipLaunchKernelGGL(k_gather_cols<8>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+    else
+        return fail(CHEBDAV_EUNSUPPORTED, "gather of more than 512 columns");
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+template <typename TS, typename TD>
+chebdav_status copy_block(const TS *Src, int64_t lds, TD *Dst, int64_t ldd, int w, int64_t n,
+                          hipStream_t st) {
+    if (w == 0 || n == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL((k_copy_block<TS, TD>), dim3(grid_for(n * w)), dim3(256), 0, st, Src, lds, Dst,
+                       ldd, w, n);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+template chebdav_status copy_block<double, double>(const double *, int64_t, double *, int64_t, int,
+                                                   int64_t, hipStream_t);
+template chebdav_status copy_block<double, float>(const double *, int64_t, float *, int64_t, int,
+                                                  int64_t, hipStream_t);
+template chebdav_status copy_block<float, double>(const float *, int64_t, double *, int64_t, int,
+                                                  int64_t, hipStream_t);
+
+chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st) {
+    if (count == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(count)), dim3(256), 0, st, p, count, v);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
+                           uint64_t first_col, hipStream_t st) {
+    if (w == 0 || n == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_philox, dim3(grid_for(n * w)), dim3(256), 0, st, X, n, w, ld, seed, first_col);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status check_finite(const double *X, int64_t ld, int w, int64_t n, int *flag,
+                            hipStream_t st) {
+    if (w == 0 || n == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_check_finite, dim3(grid_for(n * w)), dim3(256), 0, st, X, ld, w, n, flag);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+}  // namespace chebdav

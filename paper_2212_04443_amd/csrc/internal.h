@@ -1,0 +1,161 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/chebdav.h"
+
+namespace chebdav {
+
+void set_error(const char *fmt, ...);
+void clear_error();
+
+// Returns a status after recording a message; used as `return fail(...)`.
+chebdav_status fail(chebdav_status st, const char *fmt, ...);
+
+#define CD_HIP(call)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return ::chebdav::fail(CHEBDAV_EHIP, "%s failed: %s (%s:%d)", #call,        \
+                                   hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+#define CD_TRY(expr)                                                                    \
+    do {                                                                                \
+        chebdav_status s_ = (expr);                                                     \
+        if (s_ != CHEBDAV_OK) return s_;                                                \
+    } while (0)
+
+#define CD_LAUNCH_CHECK() CD_HIP(hipGetLastError())
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Device CSR pattern of S plus the degree scaling (owned by the handle).
+struct Graph {
+    int64_t n = 0;
+    int64_t nnz = 0;
+    int64_t n_isolated = 0;
+    int32_t max_deg = 0;
+    int64_t *row_ptr = nullptr;  // [n+1]
+    int32_t *col = nullptr;      // [nnz]
+    int32_t *deg = nullptr;      // [n]
+    double *dinv = nullptr;      // [n]
+    float *dinv32 = nullptr;     // [n], dinv rounded to FP32 (for the FP32 filter)
+};
+
+// Simple bump allocator over a caller-provided workspace.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    bool counting = false;  // when true, only measures (base may be null)
+    template <class T>
+    T *take(size_t count) {
+        used = align_up(used, 256);
+        T *p = counting ? nullptr : reinterpret_cast<T *>(base + used);
+        used += count * sizeof(T);
+        return p;
+    }
+    bool overflow() const { return !counting && used > cap; }
+};
+
+// ---- csr_build.hip
+chebdav_status build_graph(const int64_t *edges, int64_t n_edges, int64_t n, int on_device,
+                           hipStream_t st, Graph **out);
+void free_graph(Graph *g);
+chebdav_status dinv_table(const int32_t *deg, double *dinv, int64_t n, hipStream_t st);
+
+// ---- spmm.hip: Y = alpha * dinv .* (S (dinv .* U)) + beta U + gamma Z
+// T = element type of U and Z (and the arithmetic), TO = element type of Y.
+template <typename T, typename TO>
+chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, double gamma,
+                                const T *U, int64_t ldu, const T *Z, int64_t ldz, TO *Y,
+                                int64_t ldy, int w, hipStream_t st);
+
+// Filter driver (Alg. 3); workspace laid out by filter_layout.
+size_t filter_ws_bytes(int64_t n, int kb, chebdav_dtype dt);
+chebdav_status run_filter(const Graph *g, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                          int kb, int m, double cut, double upper, double scale_pt,
+                          chebdav_dtype dt, void *ws, size_t ws_bytes, hipStream_t st,
+                          hipEvent_t ev_begin, hipEvent_t ev_end);
+
+// ---- dense.hip
+// A column-segmented tall matrix: columns [0, p1) from X1 (ld1), [p1, p1+p2) from X2 (ld2).
+struct Seg2 {
+    const double *X1 = nullptr;
+    int64_t ld1 = 0;
+    int p1 = 0;
+    const double *X2 = nullptr;
+    int64_t ld2 = 0;
+    int p2 = 0;
+    __host__ __device__ int cols() const { return p1 + p2; }
+};
+
+// C (p x q, row-major, ldc) = Xs^T Y over n rows; Y: n x q (ldy).  Uses a
+// deterministic split over rows with partials in `partial` (gram_partial_elems).
+size_t gram_partial_elems(int64_t n, int p, int q);
+chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t n, double *C,
+                    int64_t ldc, double *partial, hipStream_t st);
+
+// Y (n x q, ldy) = alpha * Xs B + beta * Y, with B (p x q, row-major, ldb).  Y may
+// alias a column block of Xs only when q <= update_max_inplace_cols().
+int update_max_inplace_cols();
+chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha, double beta,
+                      double *Y, int64_t ldy, int q, int64_t n, hipStream_t st);
+
+// out[j] = ||X(:, j) - (Y ? Y(:, j) * theta[j] : 0)||_2 for j < w (n rows).
+size_t colnorm_partial_elems(int64_t n, int w);
+chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t ldy,
+                        const double *theta, int w, int64_t n, double *out, double *partial,
+                        hipStream_t st);
+
+// Dst(:, j) = Src(:, map[j]) for j < w, row by row (Dst may equal Src: in-place
+// permutation/compaction is safe because each row is staged first).  map on device.
+chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
+                           const int32_t *map, int w, int64_t n, hipStream_t st);
+// Dst (n x w, ldd) = Src (n x w, lds), element type conversion allowed.
+template <typename TS, typename TD>
+chebdav_status copy_block(const TS *Src, int64_t lds, TD *Dst, int64_t ldd, int w, int64_t n,
+                          hipStream_t st);
+// Fill a device array with a value.
+chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st);
+// Philox fill (see chebdav_philox_fill).
+chebdav_status philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
+                           uint64_t first_col, hipStream_t st);
+// flag[0] |= any non-finite entry in X (n x w, ld).
+chebdav_status check_finite(const double *X, int64_t ld, int w, int64_t n, int *flag,
+                            hipStream_t st);
+
+// ---- small.hip (one-workgroup kernels on small matrices)
+// Orthonormalization helper: from G = X^T X (kb x kb) and norm0 (pre-projection
+// column norms) compute Rinv (kb x kb upper triangular) with X Rinv orthonormal,
+// dep[j] = 1 for dependent columns.  scaled=1 performs the column scaling and
+// dependence tests; scaled=0 is a plain Cholesky (flags a breakdown in dep[kb]).
+chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *Rinv, int *dep,
+                         int scaled, hipStream_t st);
+// H(0:k, k-kb:k) = C (k x kb), mirrored into rows; new diagonal block symmetrized.
+chebdav_status h_insert(double *H, int64_t ldh, const double *C, int k, int kb, hipStream_t st);
+// H(0:k, 0:k) = diag(d).
+chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStream_t st);
+
+// ---- eig.hip
+size_t eig_ws_bytes(int n);
+chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, double *Y,
+                         int64_t ldy, void *ws, size_t ws_bytes, hipStream_t st);
+
+// ---- orth.hip
+size_t orth_ws_bytes(int64_t n, int ksub, int kb);
+chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int64_t n,
+                              uint64_t seed, uint64_t *next_col, int *n_replaced, void *ws,
+                              size_t ws_bytes, hipStream_t st);
+
+}  // namespace chebdav

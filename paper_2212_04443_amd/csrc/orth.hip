@@ -1,0 +1,111 @@
+// Block orthonormalization of a new block X against the basis V (Alg. 2 step 6).
+//
+// Sec. 2 orthonormalizes with DGKS, replacing numerically dependent vectors by
+// random ones.  Column-by-column Gram-Schmidt is a chain of matrix-vector
+// products; here the same result (an orthonormal basis of span((I - V V^T) X)
+// that is orthogonal to V) is reached with block operations that run as
+// matrix-matrix products over all of X:
+//   BCGS2     X <- X - V (V^T X), twice (classical Gram-Schmidt + reorthogonalization)
+//   CholQR    G = X^T X; the columns are scaled to unit norm and G = R^T R;
+//             X <- X S R^{-1}.  A column is dependent when its norm after
+//             projection is below 1e-10 of its norm before (the threshold the
+//             DGKS reading uses) or its pivot in the scaled Gram matrix is below
+//             1e-13 (then it lies, to working accuracy, in the span of the
+//             columns before it).  Dependent columns are replaced by Philox
+//             columns and everything is redone.
+//   BCGS      one more pass against V (R^{-1} may amplify the remaining
+//             non-orthogonality to V), then a second, plain CholQR.
+#include <vector>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace chebdav {
+namespace {
+
+struct OrthWs {
+    double *C, *G, *Rinv, *norm0, *part;
+    int *dep;
+};
+
+OrthWs orth_layout(Arena &a, int64_t n, int ksub, int kb) {
+    OrthWs s;
+    s.C = a.take<double>((size_t)std::max(ksub, 1) * kb);
+    s.G = a.take<double>((size_t)kb * kb);
+    s.Rinv = a.take<double>((size_t)kb * kb);
+    s.norm0 = a.take<double>(kb);
+    s.dep = a.take<int>(kb + 1);
+    size_t pe = std::max(gram_partial_elems(n, std::max(ksub, 1), kb), gram_partial_elems(n, kb, kb));
+    pe = std::max(pe, colnorm_partial_elems(n, kb));
+    s.part = a.take<double>(pe);
+    return s;
+}
+
+chebdav_status project_out(const Seg2 &V, double *X, int64_t ldx, int kb, int64_t n, const OrthWs &s,
+                           hipStream_t st) {
+    if (V.cols() == 0) return CHEBDAV_OK;
+    CD_TRY(gram(V, X, ldx, kb, n, s.C, kb, s.part, st));
+    CD_TRY(update(V, s.C, kb, -1.0, 1.0, X, ldx, kb, n, st));
+    return CHEBDAV_OK;
+}
+
+}  // namespace
+
+size_t orth_ws_bytes(int64_t n, int ksub, int kb) {
+    Arena a;
+    a.counting = true;
+    (void)orth_layout(a, n, ksub, kb);
+    return a.used + 256;
+}
+
+// Per-thread pinned host buffer used for small device-to-host reads.
+void *pinned_host(size_t bytes, int slot);
+
+chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int64_t n,
+                              uint64_t seed, uint64_t *next_col, int *n_replaced, void *ws,
+                              size_t ws_bytes, hipStream_t st) {
+    if (kb < 1 || kb > update_max_inplace_cols()) return fail(CHEBDAV_EUNSUPPORTED, "kb must be in [1, %d]", update_max_inplace_cols());
+    if (n < (int64_t)V.cols() + kb) return fail(CHEBDAV_EINVAL, "n < ksub + kb: no room for an orthonormal block");
+    const size_t need = orth_ws_bytes(n, V.cols(), kb);
+    if (ws_bytes < need) return fail(CHEBDAV_ENOMEM, "orthonormalize workspace too small (%zu < %zu)", ws_bytes, need);
+    Arena a;
+    a.base = static_cast<char *>(ws);
+    a.cap = ws_bytes;
+    const OrthWs s = orth_layout(a, n, V.cols(), kb);
+    int *hdep = static_cast<int *>(pinned_host(sizeof(int) * (kb + 1), 2));
+    if (!hdep) return fail(CHEBDAV_ENOMEM, "pinned host allocation failed");
+    Seg2 xs;
+    xs.X1 = X;
+    xs.ld1 = ldx;
+    xs.p1 = kb;
+    int replaced = 0;
+    CD_TRY(colnorms(X, ldx, nullptr, 0, nullptr, kb, n, s.norm0, s.part, st));
+    for (int attempt = 0;; ++attempt) {
+        CD_TRY(project_out(V, X, ldx, kb, n, s, st));
+        CD_TRY(project_out(V, X, ldx, kb, n, s, st));
+        CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
+        CD_TRY(chol_rinv(s.G, kb, s.norm0, s.Rinv, s.dep, 1, st));
+        CD_HIP(hipMemcpyAsync(hdep, s.dep, sizeof(int) * (kb + 1), hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+        if (!hdep[kb]) break;
+        if (attempt == 3) return fail(CHEBDAV_EBREAKDOWN, "dependent vectors persist after 3 replacement rounds");
+        std::vector<int> cols;
+        for (int j = 0; j < kb; ++j)
+            if (hdep[j]) cols.push_back(j);
+        for (int j : cols) {
+            CD_TRY(philox_fill(X + j, n, 1, ldx, seed, *next_col, st));
+            *next_col += 1;
+            ++replaced;
+            CD_TRY(colnorms(X + j, ldx, nullptr, 0, nullptr, 1, n, s.norm0 + j, s.part, st));
+        }
+    }
+    CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
+    CD_TRY(project_out(V, X, ldx, kb, n, s, st));
+    CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
+    CD_TRY(chol_rinv(s.G, kb, nullptr, s.Rinv, s.dep, 0, st));
+    CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
+    if (n_replaced) *n_replaced = replaced;
+    return CHEBDAV_OK;
+}
+
+}  // namespace chebdav

@@ -1,0 +1,139 @@
+// One-workgroup kernels on small (kb x kb or k x k) matrices.
+#include "device_util.h"
+#include "internal.h"
+
+namespace chebdav {
+namespace {
+
+constexpr int kMaxKb = 64;
+
+// Cholesky factor and inverse for Cholesky QR.
+//   scaled = 1: x_j = sqrt(G_jj) is column j's norm after projection; it is
+//     dependent if x_j < 1e-10 * norm0_j (or not finite/positive).  The
+//     remaining columns are scaled to unit norm (Gt = S G S, S = diag(1/x)) and
+//     factored, Gt = Rt^T Rt; a pivot below 1e-13 marks a column numerically
+//     dependent on the ones before it.  Rinv = S Rt^{-1}, so X Rinv has
+//     orthonormal columns.
+//   scaled = 0: plain G = R^T R, Rinv = R^{-1}; a non-positive pivot sets dep[kb].
+// dep[j] (j < kb) = 1 for dependent columns, dep[kb] = 1 if any.
+__global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G, int kb,
+                                                   const double *__restrict__ norm0,
+                                                   double *__restrict__ Rinv, int *__restrict__ dep,
+                                                   int scaled) {
+    __shared__ double A[kMaxKb][kMaxKb + 1];
+    __shared__ double s[kMaxKb];
+    __shared__ int d[kMaxKb + 1];
+    const int tid = threadIdx.x;
+    if (tid <= kb) d[tid] = 0;
+    __syncthreads();
+    if (tid < kb) {
+        if (scaled) {
+            const double x = sqrt(G[tid * kb + tid]);
+            const bool bad = !(x > 0.0) || !isfinite(x) || !(x >= 1e-10 * norm0[tid]);
+            s[tid] = bad ? 0.0 : 1.0 / x;
+            if (bad) d[tid] = 1;
+        } else {
+            s[tid] = 1.0;
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kb * kb; e += blockDim.x) {
+        const int i = e / kb, j = e % kb;
+        double v = G[e] * s[i] * s[j];
+        if (scaled && (d[i] || d[j])) v = (i == j) ? 1.0 : 0.0;  // placeholder, result discarded
+        A[i][j] = v;
+    }
+    __syncthreads();
+    // right-looking Cholesky, upper factor in the upper triangle of A
+    for (int k = 0; k < kb; ++k) {
+        __shared__ double piv;
+        if (tid == 0) {
+            double pv = A[k][k];
+            const double thr = scaled ? 1e-13 : 0.0;
+            if (!(pv > thr) || !isfinite(pv)) {
+                if (!d[k]) d[k] = 1;
+                pv = 1.0;
+            }
+            piv = sqrt(pv);
+            A[k][k] = piv;
+        }
+        __syncthreads();
+        for (int j = k + 1 + tid; j < kb; j += blockDim.x) A[k][j] /= piv;
+        __syncthreads();
+        for (int e = tid; e < (kb - k - 1) * (kb - k - 1); e += blockDim.x) {
+            const int i = k + 1 + e / (kb - k - 1), j = k + 1 + e % (kb - k - 1);
+            if (j >= i) A[i][j] -= A[k][i] * A[k][j];
+        }
+        __syncthreads();
+    }
+    // inverse of the upper triangular factor, one column per thread (in LDS)
+    __shared__ double Ri[kMaxKb][kMaxKb + 1];
+    if (tid < kb) {
+        const int j = tid;
+        for (int i = 0; i < kb; ++i) Ri[i][j] = 0.0;
+        Ri[j][j] = 1.0 / A[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+            double t = 0.0;
+            for (int l = i + 1; l <= j; ++l) t += A[i][l] * Ri[l][j];
+            Ri[i][j] = -t / A[i][i];
+        }
+        for (int i = 0; i < kb; ++i) Rinv[i * kb + j] = s[i] * Ri[i][j];
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int any = 0;
+        for (int j = 0; j < kb; ++j) any |= d[j];
+        d[kb] = any;
+    }
+    __syncthreads();
+    if (tid <= kb) dep[tid] = d[tid];
+}
+
+__global__ void k_h_insert(double *__restrict__ H, int64_t ldh, const double *__restrict__ C, int k,
+                           int kb) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * kb) return;
+    const int i = e / kb, j = e % kb;
+    const int c = k - kb + j;
+    if (i < k - kb) {
+        H[(int64_t)i * ldh + c] = C[e];
+        H[(int64_t)c * ldh + i] = C[e];
+    } else {
+        const int a = i - (k - kb);
+        H[(int64_t)i * ldh + c] = 0.5 * (C[e] + C[(int64_t)(k - kb + j) * kb + a]);
+    }
+}
+
+__global__ void k_h_set_diag(double *__restrict__ H, int64_t ldh, const double *__restrict__ dg, int k) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)k * k) return;
+    const int i = (int)(e / k), j = (int)(e % k);
+    H[(int64_t)i * ldh + j] = (i == j) ? dg[i] : 0.0;
+}
+
+}  // namespace
+
+chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *Rinv, int *dep,
+                         int scaled, hipStream_t st) {
+    if (kb < 1 || kb > kMaxKb) return fail(CHEBDAV_EUNSUPPORTED, "block size %d outside [1, %d]", kb, kMaxKb);
+    hipLaunchKernelGGL(k_chol_rinv, dim3(1), dim3(256), 0, st, G, kb, norm0, Rinv, dep, scaled);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status h_insert(double *H, int64_t ldh, const double *C, int k, int kb, hipStream_t st) {
+    const int total = k * kb;
+    hipLaunchKernelGGL(k_h_insert, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, H, ldh, C, k, kb);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStream_t st) {
+    if (k == 0) return CHEBDAV_OK;
+    const int64_t total = (int64_t)k * k;
+    hipLaunchKernelGGL(k_h_set_diag, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, H, ldh, d, k);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+}  // namespace chebdav

@@ -1,0 +1,384 @@
+// Host driver of block Chebyshev-Davidson with inner-outer restart (Alg. 2).
+//
+// Every step runs on the device; the host keeps only the integer bookkeeping
+// (kc, kact, ksub, ki), the Ritz values of the active block and the residual
+// norms of its first kb pairs, read back once per iteration (step 12).
+//
+// Readings of what the algorithm leaves open (shared with the CPU oracle):
+// ascending Ritz order everywhere; filter interval cut = low_nwb, upper =
+// upperb, scale point = lowb, first cut lowb + (upperb - lowb) k_want / n;
+// convergence ||W(:,i) - V(:,kc+i) theta_i||_2 <= tol; every converged pair
+// among the first kb is locked; low_nwb = median of the kact retained Ritz
+// values (mean of the middle two for an even count), kept if not strictly
+// inside (lowb, upperb); missing vectors are Philox columns numbered in the
+// order they are drawn; k_ri = max(floor(act_max/2), act_max - 3 kb),
+// k_ro = dim_max - 2 kb - kc, act_max = max(5 kb, 30),
+// dim_max = max(act_max + 2 kb, k_want + 30).
+//
+// Device layout (all row-major):
+//   Vl    n x (k_want + kb)   locked Ritz vectors, in locking order
+//   Va[2] n x act_max         active block V(:, kc+1 : ksub), double-buffered so
+//                             the rotation V <- V Y writes out of place
+//   W[2]  n x act_max         W = A V for the active block, double-buffered
+//   Vtmp  n x kb              the block to filter next
+// V(:, 1:ksub) of the algorithm is the pair [Vl(:, 1:kc), Va(:, 1:kact)]; the
+// locked set is sorted by eigenvalue only when the result is written.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace chebdav {
+
+void *pinned_host(size_t bytes, int slot);
+
+namespace {
+
+struct Resolved {
+    int k_want, kb, m, itmax, act_max, dim_max, k_ri, lmax;
+    double tol, upperb, lowb, low_nwb0, f32_switch_tol;
+    chebdav_dtype fdt;
+    uint64_t seed;
+    bool timing;
+};
+
+chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
+    if (!p) return fail(CHEBDAV_EINVAL, "params is NULL");
+    r.k_want = p->k_want;
+    r.kb = p->kb;
+    r.m = p->m;
+    r.itmax = p->itmax > 0 ? p->itmax : 1000;
+    r.tol = p->tol > 0 ? p->tol : 1e-8;
+    r.act_max = p->act_max > 0 ? p->act_max : std::max(5 * r.kb, 30);
+    r.dim_max = p->dim_max > 0 ? p->dim_max : std::max(r.act_max + 2 * r.kb, r.k_want + 30);
+    r.k_ri = p->k_ri > 0 ? p->k_ri : std::max(r.act_max / 2, r.act_max - 3 * r.kb);
+    r.upperb = p->upperb != 0.0 ? p->upperb : 2.0;
+    r.lowb = p->lowb;
+    r.low_nwb0 = (std::isnan(p->low_nwb0) || p->low_nwb0 <= r.lowb)
+                     ? r.lowb + (r.upperb - r.lowb) * r.k_want / (double)n
+                     : p->low_nwb0;
+    r.f32_switch_tol = p->f32_switch_tol > 0 ? p->f32_switch_tol : 1e-5;
+    r.fdt = p->filter_dtype;
+    r.seed = p->seed;
+    r.timing = p->timing != 0;
+    r.lmax = r.k_want + r.kb;
+    if (r.kb < 1 || r.k_want < 1 || r.m < 1) return fail(CHEBDAV_EINVAL, "need kb >= 1, k_want >= 1, m >= 1");
+    if (r.k_want > n) return fail(CHEBDAV_EINVAL, "k_want > n");
+    if (r.kb > update_max_inplace_cols()) return fail(CHEBDAV_EUNSUPPORTED, "kb > %d", update_max_inplace_cols());
+    if (r.k_ri < 1 || r.k_ri > r.act_max - r.kb) return fail(CHEBDAV_EINVAL, "need 1 <= k_ri <= act_max - kb");
+    if (r.dim_max < r.k_want + 2 * r.kb + 1 || r.dim_max < r.act_max)
+        return fail(CHEBDAV_EINVAL, "need dim_max >= max(k_want + 2 kb + 1, act_max)");
+    if (r.dim_max > n) return fail(CHEBDAV_EINVAL, "dim_max > n");
+    if (r.act_max > 512) return fail(CHEBDAV_EUNSUPPORTED, "act_max > 512");
+    if (!(r.lowb < r.low_nwb0 && r.low_nwb0 < r.upperb)) return fail(CHEBDAV_EINVAL, "need lowb < low_nwb0 < upperb");
+    if (r.fdt != CHEBDAV_F64 && r.fdt != CHEBDAV_F32) return fail(CHEBDAV_EINVAL, "bad filter dtype");
+    return CHEBDAV_OK;
+}
+
+struct Layout {
+    double *Vl, *Va[2], *W[2], *Vtmp, *H, *C, *Y, *D, *res, *part, *hd, *ev;
+    int32_t *map;
+    void *filt, *orthw, *eigw;
+    size_t filt_b, orth_b, eig_b;
+};
+
+Layout layout(Arena &a, int64_t n, const Resolved &r) {
+    Layout L;
+    L.Vl = a.take<double>((size_t)n * r.lmax);
+    for (int i = 0; i < 2; ++i) L.Va[i] = a.take<double>((size_t)n * r.act_max);
+    for (int i = 0; i < 2; ++i) L.W[i] = a.take<double>((size_t)n * r.act_max);
+    L.Vtmp = a.take<double>((size_t)n * r.kb);
+    L.H = a.take<double>((size_t)r.act_max * r.act_max);
+    L.C = a.take<double>((size_t)r.act_max * r.kb);
+    L.Y = a.take<double>((size_t)r.act_max * r.act_max);
+    L.D = a.take<double>(r.act_max);
+    L.res = a.take<double>(std::max(r.act_max, r.lmax));
+    L.hd = a.take<double>(r.act_max);
+    L.ev = a.take<double>(r.lmax);
+    size_t pe = std::max(gram_partial_elems(n, r.act_max, r.kb), colnorm_partial_elems(n, std::min(256, std::max(r.act_max, r.kb))));
+    L.part = a.take<double>(pe);
+    L.map = a.take<int32_t>((size_t)2 * r.act_max + 2 * r.lmax);
+    L.filt_b = std::max(filter_ws_bytes(n, r.kb, CHEBDAV_F64),
+                        r.fdt == CHEBDAV_F32 ? filter_ws_bytes(n, r.kb, CHEBDAV_F32) : 0);
+    L.filt = a.take<char>(L.filt_b);
+    L.orth_b = orth_ws_bytes(n, r.dim_max, r.kb);
+    L.orthw = a.take<char>(L.orth_b);
+    L.eig_b = eig_ws_bytes(r.act_max);
+    L.eigw = a.take<char>(L.eig_b);
+    return L;
+}
+
+double median_of(std::vector<double> v) {
+    std::sort(v.begin(), v.end());
+    const size_t h = v.size() / 2;
+    return v.size() % 2 ? v[h] : 0.5 * (v[h - 1] + v[h]);
+}
+
+struct EventPair {
+    hipEvent_t b = nullptr, e = nullptr;
+    ~EventPair() {
+        if (b) (void)hipEventDestroy(b);
+        if (e) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+chebdav_status solve_workspace_size(const Graph *g, const chebdav_params *p, size_t *bytes) {
+    Resolved r;
+    CD_TRY(resolve(p, g->n, r));
+    Arena a;
+    a.counting = true;
+    (void)layout(a, g->n, r);
+    *bytes = a.used + 256;
+    return CHEBDAV_OK;
+}
+
+chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_init, int k_init,
+                     double *evals, double *evecs, chebdav_stats *stats, void *ws, size_t ws_bytes,
+                     hipStream_t st) {
+    const auto t_start = std::chrono::steady_clock::now();
+    Resolved r;
+    CD_TRY(resolve(p, g->n, r));
+    const int64_t n = g->n;
+    const int kb = r.kb, am = r.act_max;
+    if (k_init < 0 || (k_init > 0 && !V_init)) return fail(CHEBDAV_EINVAL, "bad V_init / k_init");
+    if (!evals || !evecs) return fail(CHEBDAV_EINVAL, "evals/evecs are NULL");
+    {
+        Arena c;
+        c.counting = true;
+        (void)layout(c, n, r);
+        if (!ws || ws_bytes < c.used + 256)
+            return fail(CHEBDAV_ENOMEM, "solve workspace too small (%zu < %zu)", ws_bytes, c.used + 256);
+    }
+    Arena a;
+    a.base = static_cast<char *>(ws);
+    a.cap = ws_bytes;
+    const Layout L = layout(a, n, r);
+
+    // pinned host scratch: [0] Ritz values + residuals, [1] index maps / diagonal
+    double *h_vals = static_cast<double *>(pinned_host(sizeof(double) * (2 * am + 2 * r.lmax + 8), 0));
+    int32_t *h_map = static_cast<int32_t *>(pinned_host(sizeof(int32_t) * (2 * am + 2 * r.lmax) + sizeof(double) * (am + r.lmax), 1));
+    if (!h_vals || !h_map) return fail(CHEBDAV_ENOMEM, "pinned host allocation failed");
+    double *h_diag = reinterpret_cast<double *>(h_map + 2 * am + 2 * r.lmax);
+    int *h_flag = reinterpret_cast<int *>(h_vals + 2 * am + 2 * r.lmax);
+
+    chebdav_stats S{};
+    uint64_t next_col = 0;
+
+    // V_init must be finite
+    if (k_init > 0) {
+        int *dflag = reinterpret_cast<int *>(L.map);
+        CD_HIP(hipMemsetAsync(dflag, 0, sizeof(int), st));
+        CD_TRY(check_finite(V_init, k_init, k_init, n, dflag, st));
+        CD_HIP(hipMemcpyAsync(h_flag, dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+        if (*h_flag) return fail(CHEBDAV_EINVAL, "V_init holds NaN or Inf");
+    }
+
+    // steps 1-3
+    const double upperb = r.upperb, lowb = r.lowb;
+    double low_nwb = r.low_nwb0;
+    {
+        const int take = std::min(kb, k_init);
+        if (take) CD_TRY((copy_block<double, double>(V_init, k_init, L.Vtmp, kb, take, n, st)));
+        if (take < kb) {
+            CD_TRY(philox_fill(L.Vtmp + take, n, kb - take, kb, r.seed, next_col, st));
+            next_col += kb - take;
+            S.n_random += kb - take;
+        }
+    }
+    int ki = kb, kc = 0, ksub = 0, kact = 0, cur = 0;
+    std::vector<double> locked;  // eigenvalues in locking order (column order of Vl)
+    bool use_f64_filter = r.fdt == CHEBDAV_F64;
+    EventPair evp;
+    if (r.timing) {
+        CD_HIP(hipEventCreate(&evp.b));
+        CD_HIP(hipEventCreate(&evp.e));
+    }
+    chebdav_status result = CHEBDAV_ENOCONV;
+    int it = 0;
+    std::vector<double> D(am), res(kb);
+    while (it < r.itmax) {
+        ++it;
+        double *Xnew = L.Va[cur] + kact;
+        // step 5: filter
+        const chebdav_dtype fdt = use_f64_filter ? CHEBDAV_F64 : CHEBDAV_F32;
+        CD_TRY(run_filter(g, L.Vtmp, kb, Xnew, am, kb, r.m, low_nwb, upperb, lowb, fdt, L.filt, L.filt_b,
+                          st, evp.b, evp.e));
+        S.n_spmm_filter += r.m;
+        if (fdt == CHEBDAV_F32) S.n_spmm_filter_f32 += r.m;
+        // step 6: orthonormalize against V(:, 1:ksub) = [Vl(:, 1:kc), Va(:, 1:kact)]
+        Seg2 V;
+        V.X1 = L.Vl;
+        V.ld1 = r.lmax;
+        V.p1 = kc;
+        V.X2 = L.Va[cur];
+        V.ld2 = am;
+        V.p2 = kact;
+        int nrep = 0;
+        CD_TRY(orthonormalize(V, Xnew, am, kb, n, r.seed, &next_col, &nrep, L.orthw, L.orth_b, st));
+        S.n_replaced += nrep;
+        S.n_random += nrep;
+        if (r.timing) {
+            float ms = 0.f;
+            CD_HIP(hipEventElapsedTime(&ms, evp.b, evp.e));  // orthonormalize synchronized the stream
+            S.t_filter_ms += ms;
+            S.n_filter_launches += r.m;
+        }
+        // step 7: W(:, kact+1 : kact+kb) = A V_new
+        CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, Xnew, am, nullptr, 0, L.W[cur] + kact, am,
+                                                 kb, st)));
+        S.n_spmm_other += 1;
+        kact += kb;
+        ksub += kb;
+        // step 8: H(1:kact, kact-kb+1:kact) = V(:, kc+1:ksub)^T W(:, kact-kb+1:kact), symmetrized
+        {
+            Seg2 va;
+            va.X1 = L.Va[cur];
+            va.ld1 = am;
+            va.p1 = kact;
+            CD_TRY(gram(va, L.W[cur] + kact - kb, am, kb, n, L.C, kb, L.part, st));
+            CD_TRY(h_insert(L.H, am, L.C, kact, kb, st));
+        }
+        // step 9: H Y = Y D, ascending
+        CD_TRY(small_eig(L.H, am, kact, L.D, L.Y, am, L.eigw, L.eig_b, st));
+        const int kold = kact;
+        // step 10: inner restart
+        if (kact + kb > am) {
+            kact = r.k_ri;
+            ksub = kc + kact;
+        }
+        // step 11: rotation, out of place
+        {
+            Seg2 vs, wsg;
+            vs.X1 = L.Va[cur];
+            vs.ld1 = am;
+            vs.p1 = kold;
+            wsg.X1 = L.W[cur];
+            wsg.ld1 = am;
+            wsg.p1 = kold;
+            CD_TRY(update(vs, L.Y, am, 1.0, 0.0, L.Va[1 - cur], am, kact, n, st));
+            CD_TRY(update(wsg, L.Y, am, 1.0, 0.0, L.W[1 - cur], am, kact, n, st));
+            cur = 1 - cur;
+        }
+        // step 12: residuals of the first kb active pairs
+        const int nres = std::min(kb, kact);
+        CD_TRY(colnorms(L.W[cur], am, L.Va[cur], am, L.D, nres, n, L.res, L.part, st));
+        CD_HIP(hipMemcpyAsync(h_vals, L.D, sizeof(double) * kact, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipMemcpyAsync(h_vals + am, L.res, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < kact; ++i) D[i] = h_vals[i];
+        for (int i = 0; i < nres; ++i) res[i] = h_vals[am + i];
+        std::vector<int> conv, rest;
+        for (int i = 0; i < kact; ++i) {
+            if (i < nres && res[i] <= r.tol)
+                conv.push_back(i);
+            else
+                rest.push_back(i);
+        }
+        const int ec = (int)conv.size();
+        double min_open_res = INFINITY;
+        for (int i = 0; i < nres; ++i)
+            if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
+        if (ec) {
+            int32_t *m_conv = h_map, *m_rest = h_map + am;
+            for (int t = 0; t < ec; ++t) m_conv[t] = conv[t];
+            for (int t = 0; t < (int)rest.size(); ++t) m_rest[t] = rest[t];
+            CD_HIP(hipMemcpyAsync(L.map, h_map, sizeof(int32_t) * 2 * am, hipMemcpyHostToDevice, st));
+            // lock: append the converged Ritz vectors to Vl
+            CD_TRY(gather_cols(L.Va[cur], am, L.Vl + kc, r.lmax, L.map, ec, n, st));
+            for (int t = 0; t < ec; ++t) locked.push_back(D[conv[t]]);
+            kc += ec;
+            // steps 12/14: the non-converged columns of V and W move to the front
+            if (!rest.empty()) {
+                CD_TRY(gather_cols(L.Va[cur], am, L.Va[cur], am, L.map + am, (int)rest.size(), n, st));
+                CD_TRY(gather_cols(L.W[cur], am, L.W[cur], am, L.map + am, (int)rest.size(), n, st));
+            }
+            kact -= ec;
+        }
+        // step 13
+        if (kc >= r.k_want) {
+            result = CHEBDAV_OK;
+            break;
+        }
+        std::vector<double> Dact(kact);
+        for (int t = 0; t < kact; ++t) Dact[t] = D[rest[t]];
+        // step 16: outer restart
+        if (ksub + kb > r.dim_max) {
+            kact = r.dim_max - 2 * kb - kc;
+            ksub = kc + kact;
+        }
+        // step 15: H = diag of the retained non-converged Ritz values
+        for (int t = 0; t < kact; ++t) h_diag[t] = Dact[t];
+        if (kact) {
+            CD_HIP(hipMemcpyAsync(L.hd, h_diag, sizeof(double) * kact, hipMemcpyHostToDevice, st));
+            CD_TRY(h_set_diag(L.H, am, L.hd, kact, st));
+        }
+        // step 17: next block = [unused V_init columns, leading Ritz vectors, random]
+        {
+            const int n_init = std::max(0, std::min(ec, k_init - ki));
+            const int n_ritz = std::min(kb - ec, kact);
+            const int pad = kb - n_init - n_ritz;
+            if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, L.Vtmp, kb, n_init, n, st)));
+            if (n_ritz) CD_TRY((copy_block<double, double>(L.Va[cur], am, L.Vtmp + n_init, kb, n_ritz, n, st)));
+            if (pad) {
+                CD_TRY(philox_fill(L.Vtmp + n_init + n_ritz, n, pad, kb, r.seed, next_col, st));
+                next_col += pad;
+                S.n_random += pad;
+            }
+            ki += ec;
+        }
+        // step 18
+        if (kact) {
+            const double med = median_of(std::vector<double>(Dact.begin(), Dact.begin() + kact));
+            if (lowb < med && med < upperb) low_nwb = med;
+        }
+        // mixed precision: FP64 filtering once the leading open residual is small
+        if (!use_f64_filter && min_open_res < r.f32_switch_tol) use_f64_filter = true;
+    }
+    S.iterations = it;
+    S.converged = kc;
+    // write the k_want smallest locked pairs (or all locked ones) in ascending order
+    const int kout = std::min(kc, r.k_want);
+    CD_HIP(hipStreamSynchronize(st));  // earlier uploads from the pinned maps have completed
+    if (kout > 0) {
+        std::vector<int> ord(kc);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return locked[x] < locked[y]; });
+        for (int t = 0; t < kout; ++t) {
+            h_map[t] = ord[t];
+            h_diag[t] = locked[ord[t]];
+        }
+        CD_HIP(hipMemcpyAsync(L.map, h_map, sizeof(int32_t) * kout, hipMemcpyHostToDevice, st));
+        CD_HIP(hipMemcpyAsync(L.ev, h_diag, sizeof(double) * kout, hipMemcpyHostToDevice, st));
+        CD_TRY(gather_cols(L.Vl, r.lmax, evecs, r.k_want, L.map, kout, n, st));
+        CD_TRY((copy_block<double, double>(L.ev, 1, evals, 1, 1, kout, st)));
+        // certificate: fresh residuals ||A v - lambda v|| in chunks of <= act_max columns
+        double *tmp = L.W[1 - cur];
+        for (int c0 = 0; c0 < kout; c0 += am) {
+            const int w = std::min(am, kout - c0);
+            CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, evecs + c0, r.k_want, nullptr, 0, tmp,
+                                                     am, w, st)));
+            CD_TRY(colnorms(tmp, am, evecs + c0, r.k_want, L.ev + c0, w, n, L.res + c0, L.part, st));
+        }
+        S.n_spmm_other += 1;
+        CD_HIP(hipMemcpyAsync(h_vals, L.res, sizeof(double) * kout, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+        double mr = 0.0;
+        for (int t = 0; t < kout; ++t) mr = std::max(mr, h_vals[t]);
+        S.max_residual = mr;
+    } else {
+        S.max_residual = NAN;
+        CD_HIP(hipStreamSynchronize(st));
+    }
+    S.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    if (stats) *stats = S;
+    if (result != CHEBDAV_OK) return fail(result, "itmax reached with %d of %d pairs converged", kc, r.k_want);
+    return CHEBDAV_OK;
+}
+
+}  // namespace chebdav

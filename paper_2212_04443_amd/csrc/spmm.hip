@@ -1,0 +1,311 @@
+// Fused sparse step of the Chebyshev filter (Alg. 3) and the filter driver.
+//
+//   Y = alpha * dinv .* (S (dinv .* U)) + beta * U + gamma * Z
+//
+// S is the binary CSR pattern (Eq. 1), so a row of the product is the
+// dinv-weighted sum of the neighbours' rows of U.  Dense blocks are row-major,
+// so one neighbour row (w elements) is one contiguous run of w * sizeof(T)
+// bytes.  Mapping: a "group" of G lanes owns one matrix row; each lane holds a
+// VE-wide vector of columns (16 bytes for the vector path), so a wavefront
+// gathers 64/G neighbour rows with one load instruction per lane.  The group
+// loads up to G column indices and their dinv values cooperatively (coalesced)
+// and broadcasts them lane to lane; neighbour sums run in ascending column
+// order, so results are deterministic.  Blocks are renumbered so that each of
+// the eight XCDs walks a contiguous range of rows (the gathered rows of
+// block-structured graphs then stay in that XCD's L2).
+#include <algorithm>
+
+#include "device_util.h"
+#include "internal.h"
+
+namespace chebdav {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kXcds = 8;
+
+template <typename T, int VE>
+struct VecT;
+template <>
+struct VecT<float, 4> {
+    using type = float4;
+};
+template <>
+struct VecT<float, 1> {
+    using type = float;
+};
+template <>
+struct VecT<double, 2> {
+    using type = double2;
+};
+template <>
+struct VecT<double, 1> {
+    using type = double;
+};
+
+template <typename T, int VE>
+__device__ inline void load_vec(const T *p, T (&v)[VE]) {
+    using VT = typename VecT<T, VE>::type;
+    const VT x = *reinterpret_cast<const VT *>(p);
+    static_assert(sizeof(VT) == VE * sizeof(T), "vector size");
+    __builtin_memcpy(v, &x, sizeof(VT));
+}
+
+template <typename T, typename TO, int VE, int G>
+__global__ void __launch_bounds__(kBlock)
+    k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                const T *__restrict__ dinv, T alpha, T beta, T gamma, const T *__restrict__ U,
+                int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
+                int w) {
+    constexpr int GPB = kBlock / G;  // rows per block
+    const int lane = lane_id();
+    const int gl = lane & (G - 1);
+    // XCD-aware renumbering: gridDim.x is a multiple of 8; consecutive hardware
+    // block ids alternate XCDs, so block b works on logical block
+    // (b mod 8) * (grid / 8) + b / 8.
+    const int64_t per = gridDim.x / kXcds;
+    const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+    const int64_t r = blk * GPB + threadIdx.x / G;
+    if (r >= n) return;  // uniform within a group
+    const int c0 = gl * VE;
+    const bool active = c0 < w;
+    const int64_t beg = row_ptr[r], end = row_ptr[r + 1];
+
+    T acc[VE];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) acc[e] = T(0);
+
+    for (int64_t base = beg; base < end; base += G) {
+        const int64_t idx = base + gl;
+        int jl = 0;
+        T dl = T(0);
+        if (idx < end) {
+            jl = col[idx];
+            dl = dinv[jl];
+        }
+        const int cnt = (int)min<int64_t>(G, end - base);
+        int t = 0;
+        for (; t + 4 <= cnt; t += 4) {
+            const int j0 = __shfl(jl, t + 0, G), j1 = __shfl(jl, t + 1, G);
+            const int j2 = __shfl(jl, t + 2, G), j3 = __shfl(jl, t + 3, G);
+            const T d0 = __shfl(dl, t + 0, G), d1 = __shfl(dl, t + 1, G);
+            const T d2 = __shfl(dl, t + 2, G), d3 = __shfl(dl, t + 3, G);
+            if (active) {
+                T u0[VE], u1[VE], u2[VE], u3[VE];
+                load_vec<T, VE>(U + (int64_t)j0 * ldu + c0, u0);
+                load_vec<T, VE>(U + (int64_t)j1 * ldu + c0, u1);
+                load_vec<T, VE>(U + (int64_t)j2 * ldu + c0, u2);
+                load_vec<T, VE>(U + (int64_t)j3 * ldu + c0, u3);
+#pragma unroll
+                for (int e = 0; e < VE; ++e) {
+                    acc[e] += d0 * u0[e];
+                    acc[e] += d1 * u1[e];
+                    acc[e] += d2 * u2[e];
+                    acc[e] += d3 * u3[e];
+                }
+            }
+        }
+        for (; t < cnt; ++t) {
+            const int j0 = __shfl(jl, t, G);
+            const T d0 = __shfl(dl, t, G);
+            if (active) {
+                T u0[VE];
+                load_vec<T, VE>(U + (int64_t)j0 * ldu + c0, u0);
+#pragma unroll
+                for (int e = 0; e < VE; ++e) acc[e] += d0 * u0[e];
+            }
+        }
+    }
+    if (!active) return;
+    const T di = dinv[r];
+    T ur[VE], zr[VE];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+        ur[e] = T(0);
+        zr[e] = T(0);
+    }
+    if (beta != T(0)) load_vec<T, VE>(U + r * ldu + c0, ur);
+    if (Z != nullptr) load_vec<T, VE>(Z + r * ldz + c0, zr);
+    TO *yp = Y + r * ldy + c0;
+    if constexpr (sizeof(TO) == sizeof(T)) {
+        T y[VE];
+#pragma unroll
+        for (int e = 0; e < VE; ++e) y[e] = alpha * (di * acc[e]) + beta * ur[e] + gamma * zr[e];
+        using VT = typename VecT<T, VE>::type;
+        VT v;
+        __builtin_memcpy(&v, y, sizeof(VT));
+        *reinterpret_cast<VT *>(yp) = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < VE; ++e) yp[e] = (TO)(alpha * (di * acc[e]) + beta * ur[e] + gamma * zr[e]);
+    }
+}
+
+template <typename T, typename TO, int VE>
+chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *U, int64_t ldu,
+                         const T *Z, int64_t ldz, TO *Y, int64_t ldy, int w, hipStream_t st) {
+    int lanes = (w + VE - 1) / VE;
+    int G = 1;
+    while (G < lanes) G <<= 1;
+    const int64_t rows_per_block = kBlock / G;
+    int64_t grid = ceil_div(g->n, rows_per_block);
+    grid = ceil_div(grid, kXcds) * kXcds;
+    if (grid > INT32_MAX) return fail(CHEBDAV_EUNSUPPORTED, "grid too large");
+    const dim3 gr((unsigned)grid), bl(kBlock);
+#define CD_CASE(GG)                                                                                 \
+    case GG:                                                                                        \
+        hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG>), gr, bl, 0, st, g->n, g->row_ptr, g->col,   \
+                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w);                               \
+        break;
+    switch (G) {
+        CD_CASE(1)
+        CD_CASE(2)
+        CD_CASE(4)
+        CD_CASE(8)
+        CD_CASE(16)
+        CD_CASE(32)
+        CD_CASE(64)
+        default:
+            return fail(CHEBDAV_EUNSUPPORTED, "panel too wide");
+    }
+#undef CD_CASE
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace
+
+template <typename T, typename TO>
+chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, double gamma,
+                                const T *U, int64_t ldu, const T *Z, int64_t ldz, TO *Y,
+                                int64_t ldy, int w, hipStream_t st) {
+    if (w < 1) return fail(CHEBDAV_EINVAL, "block width must be >= 1");
+    if (ldu < w || ldy < w || (Z && ldz < w)) return fail(CHEBDAV_EINVAL, "leading dimension < width");
+    if (!U || !Y) return fail(CHEBDAV_EINVAL, "NULL block");
+    if (gamma != 0.0 && !Z) return fail(CHEBDAV_EINVAL, "Z is NULL but gamma != 0");
+    const T *dinv;
+    if constexpr (sizeof(T) == 8)
+        dinv = g->dinv;
+    else
+        dinv = g->dinv32;
+    constexpr int V = 16 / sizeof(T);
+    const T a = (T)alpha, b = (T)beta, c = (T)gamma;
+    const T *Zp = (gamma != 0.0) ? Z : nullptr;
+    for (int c0 = 0; c0 < w; c0 += 64 * V) {
+        const int pw = std::min(64 * V, w - c0);
+        const bool vec = (pw % V == 0) && (ldu % V == 0) && (ldy % V == 0) &&
+                         (!Zp || ldz % V == 0) && aligned(U + c0, 16) && aligned(Y + c0, 16) &&
+                         (!Zp || aligned(Zp + c0, 16));
+        const T *Zc = Zp ? Zp + c0 : nullptr;
+        if (vec) {
+            CD_TRY((launch_ve<T, TO, V>(g, dinv, a, b, c, U + c0, ldu, Zc, ldz, Y + c0, ldy, pw, st)));
+        } else {
+            for (int s = 0; s < pw; s += 64) {
+                const int sw = std::min(64, pw - s);
+                CD_TRY((launch_ve<T, TO, 1>(g, dinv, a, b, c, U + c0 + s, ldu, Zp ? Zc + s : nullptr, ldz,
+                                            Y + c0 + s, ldy, sw, st)));
+            }
+        }
+    }
+    return CHEBDAV_OK;
+}
+
+template chebdav_status launch_cheb_step<double, double>(const Graph *, double, double, double,
+                                                         const double *, int64_t, const double *,
+                                                         int64_t, double *, int64_t, int, hipStream_t);
+template chebdav_status launch_cheb_step<float, float>(const Graph *, double, double, double,
+                                                       const float *, int64_t, const float *,
+                                                       int64_t, float *, int64_t, int, hipStream_t);
+template chebdav_status launch_cheb_step<float, double>(const Graph *, double, double, double,
+                                                        const float *, int64_t, const float *,
+                                                        int64_t, double *, int64_t, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Filter driver (Alg. 3).  With c = (cut+upper)/2, e = (upper-cut)/2,
+// sigma_1 = e/(scale_pt - c), tau = 2/sigma_1:
+//   U_1 = (A X - c X) sigma_1 / e
+//   U_k = 2 sigma_k/e (A U_{k-1} - c U_{k-1}) - sigma_{k-1} sigma_k U_{k-2},
+//         sigma_k = 1/(tau - sigma_{k-1}),   U_0 = X.
+// Since A U = U - dinv .* S (dinv .* U), each step is one fused sparse step with
+//   alpha = -s/e, beta = s(1-c)/e, gamma = -sigma_{k-1} sigma_k (s = 2 sigma_k,
+//   and s = sigma_1, gamma = 0 for the first step).
+// Buffers: three rotating n x kb work blocks; the last step writes Y.
+// ---------------------------------------------------------------------------
+size_t filter_ws_bytes(int64_t n, int kb, chebdav_dtype dt) {
+    const size_t es = dt == CHEBDAV_F32 ? 4 : 8;
+    const size_t blk = align_up((size_t)n * kb * es, 256);
+    return blk * (dt == CHEBDAV_F32 ? 4 : 3);
+}
+
+namespace {
+template <typename T>
+chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y, int64_t ldy,
+                           int kb, int m, double cut, double upper, double scale_pt, T *bufs[3],
+                           hipStream_t st) {
+    const double e = (upper - cut) / 2.0;
+    const double c = (upper + cut) / 2.0;
+    double sigma = e / (scale_pt - c);
+    const double tau = 2.0 / sigma;
+    const int64_t ldb = kb;
+    // step 1
+    {
+        const double al = -sigma / e, be = sigma * (1.0 - c) / e;
+        if (m == 1)
+            return launch_cheb_step<T, double>(g, al, be, 0.0, x0, ldx0, nullptr, 0, Y, ldy, kb, st);
+        CD_TRY((launch_cheb_step<T, T>(g, al, be, 0.0, x0, ldx0, nullptr, 0, bufs[0], ldb, kb, st)));
+    }
+    const T *prev = x0;
+    int64_t ldp = ldx0;
+    const T *cur = bufs[0];
+    for (int k = 2; k <= m; ++k) {
+        const double sigma1 = 1.0 / (tau - sigma);
+        const double al = -2.0 * sigma1 / e;
+        const double be = 2.0 * sigma1 * (1.0 - c) / e;
+        const double ga = -sigma * sigma1;
+        if (k == m) {
+            CD_TRY((launch_cheb_step<T, double>(g, al, be, ga, cur, ldb, prev, ldp, Y, ldy, kb, st)));
+        } else {
+            T *out = bufs[(k - 1) % 3];
+            CD_TRY((launch_cheb_step<T, T>(g, al, be, ga, cur, ldb, prev, ldp, out, ldb, kb, st)));
+            prev = cur;
+            ldp = ldb;
+            cur = out;
+        }
+        sigma = sigma1;
+    }
+    return CHEBDAV_OK;
+}
+}  // namespace
+
+chebdav_status run_filter(const Graph *g, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                          int kb, int m, double cut, double upper, double scale_pt,
+                          chebdav_dtype dt, void *ws, size_t ws_bytes, hipStream_t st,
+                          hipEvent_t ev_begin, hipEvent_t ev_end) {
+    if (m < 1 || kb < 1) return fail(CHEBDAV_EINVAL, "need m >= 1 and kb >= 1");
+    if (!(scale_pt < cut && cut < upper)) return fail(CHEBDAV_EINVAL, "need scale_pt < cut < upper");
+    if (ldx < kb || ldy < kb) return fail(CHEBDAV_EINVAL, "leading dimension < kb");
+    if (dt != CHEBDAV_F64 && dt != CHEBDAV_F32) return fail(CHEBDAV_EINVAL, "bad dtype");
+    const size_t need = filter_ws_bytes(g->n, kb, dt);
+    if (ws_bytes < need || (!ws && need)) return fail(CHEBDAV_ENOMEM, "filter workspace too small (%zu < %zu)", ws_bytes, need);
+    const size_t es = dt == CHEBDAV_F32 ? 4 : 8;
+    const size_t blk = align_up((size_t)g->n * kb * es, 256);
+    char *w = static_cast<char *>(ws);
+    if (ev_begin) CD_HIP(hipEventRecord(ev_begin, st));
+    if (dt == CHEBDAV_F64) {
+        double *b[3] = {reinterpret_cast<double *>(w), reinterpret_cast<double *>(w + blk),
+                        reinterpret_cast<double *>(w + 2 * blk)};
+        CD_TRY(filter_impl<double>(g, X, ldx, Y, ldy, kb, m, cut, upper, scale_pt, b, st));
+    } else {
+        float *x32 = reinterpret_cast<float *>(w + 3 * blk);
+        CD_TRY((copy_block<double, float>(X, ldx, x32, kb, kb, g->n, st)));
+        float *b[3] = {reinterpret_cast<float *>(w), reinterpret_cast<float *>(w + blk),
+                       reinterpret_cast<float *>(w + 2 * blk)};
+        CD_TRY(filter_impl<float>(g, x32, kb, Y, ldy, kb, m, cut, upper, scale_pt, b, st));
+    }
+    if (ev_end) CD_HIP(hipEventRecord(ev_end, st));
+    return CHEBDAV_OK;
+}
+
+}  // namespace chebdav

@@ -1,0 +1,66 @@
+"""GPU: block orthonormalization (Alg. 2 step 6) by its invariants, and the
+replacement of exactly dependent columns (same count as the oracle's DGKS)."""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _basis(n, k, seed):
+    q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, k)))
+    return np.ascontiguousarray(q)
+
+
+def _run(cd, V, X, seed=0, first=0):
+    import torch
+    Vt = torch.from_numpy(V).cuda() if V is not None and V.shape[1] else None
+    Xt = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    rep = cd.orthonormalize(Vt, Xt, seed=seed, first_random_col=first)
+    return Xt.cpu().numpy(), rep
+
+
+@pytest.mark.parametrize("n,ksub,kb", [(2000, 40, 8), (50_000, 224, 32), (100_000, 384, 64), (777, 0, 5)])
+def test_invariants_and_span(cd, dev, n, ksub, kb):
+    V = _basis(n, ksub, 0) if ksub else np.zeros((n, 0))
+    X = np.random.default_rng(1).standard_normal((n, kb))
+    print("case orth n=%d ksub=%d kb=%d" % (n, ksub, kb), flush=True)
+    Q, rep = _run(cd, V, X)
+    assert rep == 0
+    assert np.linalg.norm(Q.T @ Q - np.eye(kb), 2) <= 10 * kb * EPS
+    if ksub:
+        assert np.linalg.norm(V.T @ Q, 2) <= 10 * ksub * EPS
+    Xp = X - V @ (V.T @ X) if ksub else X
+    assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-12 * np.linalg.norm(Xp)
+
+
+def test_ill_conditioned_mostly_in_span(cd, dev):
+    n, kb = 3000, 6
+    V = _basis(n, 20, 4)
+    base = np.random.default_rng(5).standard_normal((n, 1))
+    X = base + 1e-5 * np.random.default_rng(6).standard_normal((n, kb))
+    X = X + V @ np.random.default_rng(7).standard_normal((20, kb)) * 1e3
+    Q, rep = _run(cd, V, X)
+    assert rep == 0
+    assert np.linalg.norm(Q.T @ Q - np.eye(kb), 2) <= 100 * kb * EPS
+    assert np.linalg.norm(V.T @ Q, 2) <= 100 * 20 * EPS
+    Xp = X - V @ (V.T @ X)
+    assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-9 * np.linalg.norm(Xp)
+
+
+def test_exactly_dependent_columns(cd, oracle_mod, dev):
+    n, kb = 1500, 6
+    V = _basis(n, 10, 8)
+    X = np.random.default_rng(9).standard_normal((n, kb))
+    X[:, 2] = X[:, 0]
+    X[:, 4] = V @ np.arange(1.0, 11.0)
+    X[:, 5] = 0.0
+    Q, rep = _run(cd, V, X, seed=2, first=100)
+    _, rep_oracle, _ = oracle_mod.dgks(np.asfortranarray(V), X, seed=2, next_col=100)
+    assert rep == rep_oracle == 3
+    assert np.linalg.norm(Q.T @ Q - np.eye(kb), 2) <= 10 * kb * EPS
+    assert np.linalg.norm(V.T @ Q, 2) <= 100 * EPS
+    # the independent columns keep their span
+    keep = X[:, [0, 1, 3]] - V @ (V.T @ X[:, [0, 1, 3]])
+    assert np.linalg.norm(keep - Q @ (Q.T @ keep)) <= 1e-12 * np.linalg.norm(keep)

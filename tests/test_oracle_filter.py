@@ -61,8 +61,8 @@ def test_filter_cycle_fourier_modes(oracle_mod, n, j, mdeg, cut):
     """On the cycle C_n, cos(2 pi j x / n) is an eigenvector with eigenvalue
     1 - cos(2 pi j / n), so the filter must return p_m(lambda_j) times it."""
     g = oracle_mod.build_csr(synth.cycle_graph(n), n)
-    x = np.arange(n)
-    X = np.stack([np.cos(2 * math.pi * j * x / n), np.sin(2 * math.pi * j * x / n)], 1)
+    ph = 2 * math.pi * ((j * np.arange(n, dtype=np.int64)) % n) / n   # exact phase reduction
+    X = np.stack([np.cos(ph), np.sin(ph)], 1)
     lam = 1 - math.cos(2 * math.pi * j / n)
     got = oracle_mod.cheb_filter(g, X, mdeg, cut, 2.0, 0.0)
     f = p_m(mdeg, np.array([lam]), cut, 2.0, 0.0)[0]
