@@ -6,7 +6,7 @@
 //   3. eigenvectors of T by inverse iteration with the LU factorization (with
 //      partial pivoting) of T - w I, one thread per eigenvector, factors stored
 //      interleaved across threads so every access is coalesced;
-//   4. modified Gram-Schmidt inside tight clusters (gap < 1e-6 ||T||);
+//   4. modified Gram-Schmidt inside tight clusters (gap <= 1e-6 ||T||);
 //   5. back-transformation Y = Q Z, one wavefront per eigenvector;
 //   6. two Newton-Schulz steps Y <- Y (3 I - Y^T Y)/2 restore orthogonality to
 //      rounding level (inverse-iteration vectors of distinct eigenvalues are
@@ -199,7 +199,7 @@ __global__ void k_inviter(const double *__restrict__ d, const double *__restrict
     const double tight = kTightRel * tnorm;
     const double pert = 10.0 * kEps * fmax(tnorm, DBL_MIN);
     int pos = 0;
-    for (int i = j - 1; i >= 0 && w[i + 1] - w[i] < tight; --i) ++pos;
+    for (int i = j - 1; i >= 0 && w[i + 1] - w[i] <= tight; --i) ++pos;
     const double lam = w[j] + pert * pos;
     const double tiny = kEps * fmax(tnorm, DBL_MIN);
 #define IX(i) ((int64_t)(i) * n + j)
@@ -277,10 +277,10 @@ __global__ void __launch_bounds__(256) k_cluster_mgs(const double *__restrict__ 
                                                      double *__restrict__ Zv) {
     const int j = blockIdx.x;
     const double tight = kTightRel * par[0];
-    if (!(j == 0 || w[j] - w[j - 1] >= tight)) return;
-    if (j + 1 >= n || w[j + 1] - w[j] >= tight) return;
+    if (!(j == 0 || w[j] - w[j - 1] > tight)) return;
+    if (j + 1 >= n || w[j + 1] - w[j] > tight) return;
     int end = j + 1;
-    while (end < n && w[end] - w[end - 1] < tight) ++end;
+    while (end < n && w[end] - w[end - 1] <= tight) ++end;
     for (int c = j + 1; c < end; ++c) {
         double *zc = Zv + (int64_t)c * n;
         for (int pass = 0; pass < 2; ++pass) {

@@ -162,3 +162,32 @@ def test_f32_form_sbm20k(cd, oracle_mod, dev):
     assert np.abs(ev - ref.evals).max() <= 1e-10
     assert sin_max_angle(ref.evecs, V) <= 1e-6
     assert st["n_spmm_filter_f32"] > 0
+
+
+_full = {}
+
+
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_sbm200k_full_size_parity(cd, oracle_mod, dev, form):
+    """The 200k-node, 32-block workload at full size (k = kb = 32, m = 15),
+    in the configuration the benchmark times, against the full oracle solve."""
+    e, n, cfg = synth.make_config_graph("sbm200k")
+    if "ref" not in _full:
+        o = oracle_mod.build_csr(e, n)
+        _full["o"] = o
+        _full["ref"] = oracle_mod.bchdav(o, oracle_mod.Params(k_want=32, kb=32, m=15, seed=1))
+    o, ref = _full["o"], _full["ref"]
+    o_csr_cache[0] = o
+    print("case sbm200k full solve %s" % form, flush=True)
+    _, ev, V, st = _gpu_solve(cd, e, n, k_want=32, kb=32, m=15, seed=1,
+                              filter_dtype=cd.F64 if form == "f64" else cd.F32)
+    res = _fresh_residuals(oracle_mod, ev, V)
+    print("sbm200k %s: iters gpu %d oracle %d; max res %.3g; max dlam %.3g; angle %.3g" %
+          (form, st["iterations"], ref.iterations, res.max(), np.abs(ev - ref.evals).max(),
+           sin_max_angle(ref.evecs, V)))
+    assert res.max() <= 1e-8
+    assert np.abs(ev - ref.evals).max() <= 1e-10
+    assert sin_max_angle(ref.evecs, V) <= 1e-6
+    assert np.linalg.norm(V.T @ V - np.eye(32), 2) <= 1e-12
+    if form == "f64":
+        assert abs(st["iterations"] - ref.iterations) <= 2
