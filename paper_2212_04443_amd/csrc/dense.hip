@@ -16,131 +16,164 @@ namespace chebdav {
 namespace {
 
 constexpr int TB = 64;   // tile edge (rows / columns of the output tile)
-constexpr int KC = 16;   // reduction chunk
-constexpr int NT = 256;  // threads per block (16 x 16, each a 4 x 4 sub-tile)
+constexpr int NT = 256;  // threads per block of the column-norm kernel
 
 __device__ inline double seg_load(const Seg2 &s, int64_t row, int c) {
     return c < s.p1 ? s.X1[row * s.ld1 + c] : s.X2[row * s.ld2 + (c - s.p1)];
 }
 
-// Partial Gram: part[z][i][j] = sum over rows of split z of Xs[row][i] Y[row][j].
-__global__ void __launch_bounds__(NT) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy,
-                                             int q, int64_t n, int64_t rows_per_split,
-                                             double *__restrict__ part) {
-    __shared__ double sa[KC][TB + 1];
-    __shared__ double sb[KC][TB + 1];
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// v_mfma_f64_16x16x4f64 lane layout (one wavefront; checked on gfx950): A
+// (16 x 4) element (i, k) in lane i + 16 k; B (4 x 16) element (k, j) in lane
+// j + 16 k; the 16 x 16 result element (i, j) in lane j + 16 (i % 4), register i / 4.
+__device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Partial Gram on matrix cores: one wavefront computes the 64 x (16 TQT) tile
+// (i0.., j0..) of Xs^T Y over the rows of split z, four rows per MFMA step, with
+// both operands loaded straight from the row-major blocks (lane k*16 + c reads
+// column c of row k: four 128-byte row segments per load).
+template <int TQT>
+__global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy, int q,
+                                             int64_t n, int64_t rows_per_split, double *__restrict__ part) {
     const int p = xs.cols();
-    const int i0 = blockIdx.x * TB, j0 = blockIdx.y * TB;
+    const int lane = threadIdx.x;
+    const int kr = lane >> 4, cc = lane & 15;
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * (16 * TQT);
     const int64_t r_beg = (int64_t)blockIdx.z * rows_per_split;
     const int64_t r_end = min(n, r_beg + rows_per_split);
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
-    for (int64_t r0 = r_beg; r0 < r_end; r0 += KC) {
+    d4_t acc[4][TQT];
 #pragma unroll
-        for (int t = 0; t < (KC * TB) / NT; ++t) {
-            const int e = threadIdx.x + t * NT;
-            const int kk = e / TB, c = e % TB;
-            const int64_t row = r0 + kk;
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < TQT; ++u) acc[t][u] = d4_t{0.0, 0.0, 0.0, 0.0};
+    bool colv[4], colw[TQT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) colv[t] = i0 + 16 * t + cc < p;
+#pragma unroll
+    for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
+    for (int64_t r = r_beg; r < r_end; r += 8) {
+        double a[2][4], b[2][TQT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t row = r + 4 * h + kr;
             const bool rv = row < r_end;
-            sa[kk][c] = (rv && i0 + c < p) ? seg_load(xs, row, i0 + c) : 0.0;
-            sb[kk][c] = (rv && j0 + c < q) ? Y[row * ldy + j0 + c] : 0.0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[h][t] = (rv && colv[t]) ? seg_load(xs, row, i0 + 16 * t + cc) : 0.0;
+#pragma unroll
+            for (int u = 0; u < TQT; ++u) b[h][u] = (rv && colw[u]) ? Y[row * ldy + j0 + 16 * u + cc] : 0.0;
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            double a[4], b[4];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = sa[kk][ty * 4 + u];
-                b[u] = sb[kk][tx * 4 + u];
-            }
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-        }
-        __syncthreads();
+                for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
     }
     double *out = part + (int64_t)blockIdx.z * p * q;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = i0 + ty * 4 + u, j = j0 + tx * 4 + v;
-            if (i < p && j < q) out[(int64_t)i * q + j] = acc[u][v];
-        }
+        for (int u = 0; u < TQT; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = i0 + 16 * t + kr + 4 * v, j = j0 + 16 * u + cc;
+                if (i < p && j < q) out[(int64_t)i * q + j] = acc[t][u][v];
+            }
 }
 
-__global__ void k_gram_reduce(const double *__restrict__ part, int splits, int p, int q,
-                              double *__restrict__ C, int64_t ldc) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)p * q) return;
+// Fixed-order reduction of S partial arrays of E elements: thread group zg sums
+// z = zg, zg + 8, ... and the eight group sums are added in order.
+// MODE 0 writes C[(e / q) * ldc + e % q] (a Gram tile); MODE 1 writes sqrt(sum) to C[e].
+template <int MODE>
+__global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part, int S, int64_t E, int q,
+                                                double *__restrict__ C, int64_t ldc) {
+    constexpr int EB = 32, ZG = 8;
+    __shared__ double sh[ZG][EB];
+    const int el = threadIdx.x % EB, zg = threadIdx.x / EB;
+    const int64_t e = (int64_t)blockIdx.x * EB + el;
     double s = 0.0;
-    for (int z = 0; z < splits; ++z) s += part[(int64_t)z * p * q + e];
-    C[(e / q) * ldc + (e % q)] = s;
+    if (e < E)
+        for (int z = zg; z < S; z += ZG) s += part[(int64_t)z * E + e];
+    sh[zg][el] = s;
+    __syncthreads();
+    if (zg == 0 && e < E) {
+        double t = 0.0;
+#pragma unroll
+        for (int g = 0; g < ZG; ++g) t += sh[g][el];
+        if (MODE == 0)
+            C[(e / q) * ldc + (e % q)] = t;
+        else
+            C[e] = sqrt(t);
+    }
 }
 
+// Row splits of a Gram product: about 1024 wavefronts in total, at least 512 rows each.
 int gram_splits(int64_t n, int p, int q) {
     const int tiles = (int)(ceil_div(p, TB) * ceil_div(q, TB));
     int64_t s = std::max<int64_t>(1, 1024 / tiles);
-    s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n, 256)));
+    s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n, 512)));
     return (int)s;
 }
 
-// Y = alpha Xs B + beta Y; one block owns a 64-row x 64-column tile of Y and
-// writes it only after it has read every row of Xs it needs.
-__global__ void __launch_bounds__(NT) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
-                                               double alpha, double beta, double *Y, int64_t ldy,
-                                               int q, int64_t n) {
-    __shared__ double sx[TB][KC + 1];
-    __shared__ double sb[KC][TB + 1];
+// Y = alpha Xs B + beta Y on matrix cores: one wavefront owns a 64-row x
+// (16 TQT)-column tile of Y, accumulates over all p columns of Xs (four per MFMA
+// step; lane k*16 + i reads row i, column k: consecutive lanes of a row read
+// adjacent elements) and writes the tile only at the end, so Y may alias Xs when
+// it has a single column tile.
+template <int TQT>
+__global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
+                                               double alpha, double beta, double *Y, int64_t ldy, int q,
+                                               int64_t n) {
     const int p = xs.cols();
-    const int64_t r0 = (int64_t)blockIdx.x * TB;
-    const int j0 = blockIdx.y * TB;
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-    double acc[4][4] = {};
-    for (int k0 = 0; k0 < p; k0 += KC) {
+    const int lane = threadIdx.x;
+    const int kr = lane >> 4, cc = lane & 15;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int j0 = blockIdx.y * (16 * TQT);
+    d4_t acc[4][TQT];
 #pragma unroll
-        for (int t = 0; t < (KC * TB) / NT; ++t) {
-            const int e = threadIdx.x + t * NT;
-            {  // X tile: 64 rows x 16 columns
-                const int rr = e / KC, kk = e % KC;
-                const int64_t row = r0 + rr;
-                sx[rr][kk] = (row < n && k0 + kk < p) ? seg_load(xs, row, k0 + kk) : 0.0;
-            }
-            {  // B tile: 16 rows x 64 columns
-                const int kk = e / TB, c = e % TB;
-                sb[kk][c] = (k0 + kk < p && j0 + c < q) ? B[(int64_t)(k0 + kk) * ldb + j0 + c] : 0.0;
-            }
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int u = 0; u < TQT; ++u) acc[t][u] = d4_t{0.0, 0.0, 0.0, 0.0};
+    bool rowv[4], colw[TQT];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) rowv[t] = r0 + 16 * t + cc < n;
+#pragma unroll
+    for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
+    for (int k0 = 0; k0 < p; k0 += 8) {
+        double a[2][4], b[2][TQT];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int kk = k0 + 4 * h + kr;
+            const bool kv = kk < p;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[h][t] = (kv && rowv[t]) ? seg_load(xs, r0 + 16 * t + cc, kk) : 0.0;
+#pragma unroll
+            for (int u = 0; u < TQT; ++u) b[h][u] = (kv && colw[u]) ? B[(int64_t)kk * ldb + j0 + 16 * u + cc] : 0.0;
         }
-        __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < KC; ++kk) {
-            double a[4], b[4];
+        for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = sx[ty * 4 + u][kk];
-                b[u] = sb[kk][tx * 4 + u];
-            }
+            for (int t = 0; t < 4; ++t)
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-        }
-        __syncthreads();
+                for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int64_t row = r0 + ty * 4 + u;
-        if (row >= n) continue;
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int j = j0 + tx * 4 + v;
-            if (j >= q) continue;
-            double *y = Y + row * ldy + j;
-            *y = beta == 0.0 ? alpha * acc[u][v] : alpha * acc[u][v] + beta * (*y);
+            const int64_t row = r0 + 16 * t + kr + 4 * v;
+            if (row >= n) continue;
+#pragma unroll
+            for (int u = 0; u < TQT; ++u) {
+                const int j = j0 + 16 * u + cc;
+                if (j >= q) continue;
+                double *y = Y + row * ldy + j;
+                *y = beta == 0.0 ? alpha * acc[t][u][v] : alpha * acc[t][u][v] + beta * (*y);
+            }
         }
-    }
 }
 
 // Column sums of squares of (X - Y diag(theta)) over a row range per block.
@@ -171,16 +204,7 @@ __global__ void __launch_bounds__(NT) k_colnorm(const double *__restrict__ X, in
     }
 }
 
-__global__ void k_colnorm_reduce(const double *__restrict__ part, int blocks, int w,
-                                 double *__restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= w) return;
-    double s = 0.0;
-    for (int b = 0; b < blocks; ++b) s += part[(int64_t)b * w + j];
-    out[j] = sqrt(s);
-}
-
-constexpr int kColnormBlocks = 512;
+constexpr int kColnormBlocks = 1024;
 
 // One wavefront per row: stage the row's selected entries, then write them.
 template <int PER_LANE>
@@ -275,10 +299,10 @@ unsigned grid_for(int64_t total) {
 }  // namespace
 
 // Upper bound of splits * p' * q' over all p' <= p, q' <= q: splits * tiles <=
-// max(tiles, 1024) and p' q' <= tiles * TB * TB.
+// max(tiles, 2048) and p' q' <= tiles * TB * TB.
 size_t gram_partial_elems(int64_t, int p, int q) {
     const int64_t tiles = ceil_div(std::max(p, 1), TB) * ceil_div(std::max(q, 1), TB);
-    return (size_t)std::max<int64_t>(tiles, 1024) * TB * TB;
+    return (size_t)std::max<int64_t>(tiles, 2048) * TB * TB;
 }
 
 chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t n, double *C,
@@ -286,13 +310,19 @@ chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t
     const int p = Xs.cols();
     if (p == 0 || q == 0) return CHEBDAV_OK;
     const int splits = gram_splits(n, p, q);
-    const int64_t rps = ceil_div(ceil_div(n, splits), KC) * KC;
-    const dim3 grid((unsigned)ceil_div(p, TB), (unsigned)ceil_div(q, TB), (unsigned)splits);
-    hipLaunchKernelGGL(k_gram, grid, dim3(NT), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    const int64_t rps = ceil_div(ceil_div(n, splits), 8) * 8;
+    const int qt = std::min(q, TB);
+    const dim3 grid((unsigned)ceil_div(p, TB), (unsigned)ceil_div(q, qt), (unsigned)splits);
+    if (qt <= 16)
+        hipLaunchKernelGGL(k_gram<1>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    else if (qt <= 32)
+        hipLaunchKernelGGL(k_gram<2>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    else
+        hipLaunchKernelGGL(k_gram<4>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
     CD_LAUNCH_CHECK();
     const int64_t pq = (int64_t)p * q;
-    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)ceil_div(pq, 256)), dim3(256), 0, st, partial,
-                       splits, p, q, C, ldc);
+    hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 32)), dim3(256), 0, st, partial, splits, pq,
+                       q, C, ldc);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
@@ -306,8 +336,14 @@ chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha
         if (beta == 1.0) return CHEBDAV_OK;
         return fail(CHEBDAV_EUNSUPPORTED, "update with an empty basis");
     }
-    const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, TB));
-    hipLaunchKernelGGL(k_update, grid, dim3(NT), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    const int qt = std::min(q, TB);
+    const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, qt));
+    if (qt <= 16)
+        hipLaunchKernelGGL(k_update<1>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    else if (qt <= 32)
+        hipLaunchKernelGGL(k_update<2>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    else
+        hipLaunchKernelGGL(k_update<4>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
@@ -320,13 +356,13 @@ chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t l
     if (w == 0) return CHEBDAV_OK;
     for (int c0 = 0; c0 < w; c0 += NT) {
         const int pw = std::min(NT, w - c0);
-        const int blocks = (int)std::min<int64_t>(kColnormBlocks, std::max<int64_t>(1, ceil_div(n, 64)));
+        const int blocks = (int)std::min<int64_t>(kColnormBlocks, std::max<int64_t>(1, ceil_div(n, 256)));
         const int64_t rpb = ceil_div(n, blocks);
         hipLaunchKernelGGL(k_colnorm, dim3(blocks), dim3(NT), 0, st, X + c0, ldx, Y ? Y + c0 : nullptr,
                            ldy, theta ? theta + c0 : nullptr, pw, n, rpb, partial);
         CD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_colnorm_reduce, dim3((unsigned)ceil_div(pw, 256)), dim3(256), 0, st,
-                           partial, blocks, pw, out + c0);
+        hipLaunchKernelGGL(k_reduce<1>, dim3((unsigned)ceil_div(pw, 32)), dim3(256), 0, st, partial, blocks,
+                           (int64_t)pw, 1, out + c0, 1);
         CD_LAUNCH_CHECK();
     }
     return CHEBDAV_OK;

@@ -1,14 +1,14 @@
 // Symmetric eigendecomposition H = Y diag(w) Y^T of the small Rayleigh-quotient
 // matrix (Alg. 2 step 9), ascending.  Pipeline:
-//   1. Householder tridiagonalization Q^T H Q = T (one workgroup; H stays in
-//      L2, the current Householder vector in LDS);
-//   2. eigenvalues of T by bisection on Sturm counts, one thread per eigenvalue;
+//   1. Householder tridiagonalization Q^T H Q = T (one workgroup; the working
+//      matrix in LDS up to n = 128, else in L2; the Householder vector in LDS);
+//   2. eigenvalues of T by multisection on Sturm counts, one wavefront per
+//      eigenvalue (64 points per round);
 //   3. eigenvectors of T by inverse iteration with the LU factorization (with
-//      partial pivoting) of T - w I, one thread per eigenvector, factors stored
-//      interleaved across threads so every access is coalesced;
+//      partial pivoting) of T - w I, one wavefront per eigenvector, factors in LDS;
 //   4. modified Gram-Schmidt inside tight clusters (gap <= 1e-6 ||T||);
 //   5. back-transformation Y = Q Z, one wavefront per eigenvector;
-//   6. two Newton-Schulz steps Y <- Y (3 I - Y^T Y)/2 restore orthogonality to
+//   6. one Newton-Schulz step Y <- Y (3 I - Y^T Y)/2 restores orthogonality to
 //      rounding level (inverse-iteration vectors of distinct eigenvalues are
 //      orthogonal only to about eps ||T|| / gap).
 #include <cfloat>
@@ -20,12 +20,12 @@ namespace chebdav {
 namespace {
 
 constexpr int kMaxN = 1024;
+constexpr int kLdsMaxN = 128;  // working matrix in LDS (n^2 doubles) up to this size
 constexpr double kEps = DBL_EPSILON * 0.5;
 constexpr double kTightRel = 1e-6;
 
 struct EigWs {
-    double *A, *Vh, *Zv, *dl, *dd, *du, *du2, *x;
-    int *ipiv;
+    double *A, *Vh, *Zv;
     double *d, *e, *tau, *w, *par, *G, *Bm, *T, *part;
 };
 
@@ -35,12 +35,6 @@ EigWs eig_layout(Arena &a, int n) {
     s.A = a.take<double>(nn);
     s.Vh = a.take<double>(nn);
     s.Zv = a.take<double>(nn);
-    s.dl = a.take<double>(nn);
-    s.dd = a.take<double>(nn);
-    s.du = a.take<double>(nn);
-    s.du2 = a.take<double>(nn);
-    s.x = a.take<double>(nn);
-    s.ipiv = a.take<int>(nn);
     s.d = a.take<double>(n);
     s.e = a.take<double>(n);
     s.tau = a.take<double>(n);
@@ -53,29 +47,37 @@ EigWs eig_layout(Arena &a, int n) {
     return s;
 }
 
-__global__ void __launch_bounds__(1024) k_tridiag(const double *__restrict__ H, int64_t ldh, int n,
-                                                  double *__restrict__ A, double *__restrict__ Vh,
-                                                  double *__restrict__ d, double *__restrict__ e,
-                                                  double *__restrict__ tau) {
-    __shared__ double v[kMaxN];
-    __shared__ double wsh[kMaxN];
+// Householder step k of the lower tridiagonalization, on the n x n working
+// matrix A (row-major, leading dimension n): v = x - alpha e1 for the column
+// x = A(k+1:n, k), p = tau A v, w = p - (tau/2)(p^T v) v, A <- A - v w^T - w v^T.
+// The update is done by rows (each wavefront owns rows i = wave, wave + nw, ...;
+// lanes run over columns), the product A v by columns (no cross-lane sums).
+__device__ __forceinline__ void tridiag_run(double *A, const double *__restrict__ H, int64_t ldh, int n,
+                                            double *__restrict__ Vh, double *__restrict__ d,
+                                            double *__restrict__ e, double *__restrict__ tau,
+                                            double *v, double *wsh, double *red) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = lane_id(), wv = tid / kWave, nw = nt / kWave;
-    for (int q = tid; q < n * n; q += nt) A[q] = H[(int64_t)(q / n) * ldh + (q % n)];
+    for (int i = wv; i < n; i += nw)
+        for (int j = lane; j < n; j += kWave) A[i * n + j] = H[(int64_t)i * ldh + j];
     __syncthreads();
     for (int k = 0; k + 2 < n; ++k) {
         const int m = n - k - 1;
-        for (int i = tid; i < m; i += nt) v[i] = A[(k + 1 + i) * n + k];
-        __syncthreads();
+        const int base = (k + 1) * n + (k + 1);  // A(k+1, k+1)
         double part = 0.0;
-        for (int i = 1 + tid; i < m; i += nt) part += v[i] * v[i];
-        const double ss = block_sum(part);
+        for (int i = tid; i < m; i += nt) {
+            const double xi = A[(k + 1 + i) * n + k];
+            v[i] = xi;
+            if (i > 0) part += xi * xi;
+        }
+        const double ss = block_sum(part);  // also makes v visible
         const double x0 = v[0];
+        const double dk = A[k * n + k];
         if (ss == 0.0) {
             if (tid == 0) {
                 tau[k] = 0.0;
                 e[k] = x0;
-                d[k] = A[k * n + k];
+                d[k] = dk;
             }
             for (int i = tid; i < m; i += nt) Vh[k * n + i] = 0.0;
             __syncthreads();
@@ -84,30 +86,39 @@ __global__ void __launch_bounds__(1024) k_tridiag(const double *__restrict__ H, 
         const double alpha = -copysign(sqrt(x0 * x0 + ss), x0);
         const double v0 = x0 - alpha;
         const double t = 2.0 / (v0 * v0 + ss);
-        __syncthreads();
         if (tid == 0) {
-            v[0] = v0;
             tau[k] = t;
             e[k] = alpha;
-            d[k] = A[k * n + k];
+            d[k] = dk;
         }
+        // p = t A v (A symmetric, so p_i = t sum_j A(j, i) v_j): threads own
+        // columns i, JG groups of threads split the j range, partial sums meet in red
+        if (tid == 0) v[0] = v0;
         __syncthreads();
-        for (int i = wv; i < m; i += nw) {
-            const double *row = A + (k + 1 + i) * n + (k + 1);
-            double s = 0.0;
-            for (int j = lane; j < m; j += kWave) s += row[j] * v[j];
-            s = wave_sum(s);
-            if (lane == 0) wsh[i] = t * s;
+        {
+            constexpr int JG = 4;
+            const int cw = nt / JG;
+            const int g = tid / cw, c = tid % cw;
+            for (int i0 = 0; i0 < m; i0 += cw) {
+                const int i = i0 + c;
+                double sacc = 0.0;
+                if (i < m)
+                    for (int j = g; j < m; j += JG) sacc += A[base + j * n + i] * v[j];
+                red[g * cw + c] = sacc;
+                __syncthreads();
+                if (g == 0 && i < m) wsh[i] = t * (red[c] + red[cw + c] + red[2 * cw + c] + red[3 * cw + c]);
+                __syncthreads();
+            }
         }
-        __syncthreads();
         part = 0.0;
         for (int i = tid; i < m; i += nt) part += wsh[i] * v[i];
         const double K = 0.5 * t * block_sum(part);
         for (int i = tid; i < m; i += nt) wsh[i] -= K * v[i];
         __syncthreads();
-        for (int q = tid; q < m * m; q += nt) {
-            const int i = q / m, j = q % m;
-            A[(k + 1 + i) * n + (k + 1 + j)] -= v[i] * wsh[j] + wsh[i] * v[j];
+        for (int i = wv; i < m; i += nw) {
+            double *row = A + base + i * n;
+            const double vi = v[i], wi = wsh[i];
+            for (int j = lane; j < m; j += kWave) row[j] -= vi * wsh[j] + wi * v[j];
         }
         for (int i = tid; i < m; i += nt) Vh[k * n + i] = v[i];
         __syncthreads();
@@ -124,18 +135,21 @@ __global__ void __launch_bounds__(1024) k_tridiag(const double *__restrict__ H, 
     }
 }
 
-__device__ inline void gersh(const double *d, const double *e, int n, double &gl, double &gu,
-                             double &emax2) {
-    gl = DBL_MAX;
-    gu = -DBL_MAX;
-    emax2 = 0.0;
-    for (int i = 0; i < n; ++i) {
-        const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
-        const double er = i + 1 < n ? fabs(e[i]) : 0.0;
-        gl = fmin(gl, d[i] - el - er);
-        gu = fmax(gu, d[i] + el + er);
-        emax2 = fmax(emax2, er * er);
-    }
+// Working matrix in LDS (n <= kLdsMaxN).
+__global__ void __launch_bounds__(512) k_tridiag_lds(const double *__restrict__ H, int64_t ldh, int n,
+                                                     double *__restrict__ Vh, double *__restrict__ d,
+                                                     double *__restrict__ e, double *__restrict__ tau) {
+    __shared__ double As[kLdsMaxN * kLdsMaxN];
+    __shared__ double v[kLdsMaxN], wsh[kLdsMaxN], red[512];
+    tridiag_run(As, H, ldh, n, Vh, d, e, tau, v, wsh, red);
+}
+
+// Working matrix in global memory (L2-resident), any n <= kMaxN.
+__global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, int64_t ldh, int n,
+                                                 double *Ag, double *__restrict__ Vh, double *__restrict__ d,
+                                                 double *__restrict__ e, double *__restrict__ tau) {
+    __shared__ double v[kMaxN], wsh[kMaxN], red[512];
+    tridiag_run(Ag, H, ldh, n, Vh, d, e, tau, v, wsh, red);
 }
 
 // Number of eigenvalues of T smaller than x (Sturm sequence).
@@ -152,28 +166,58 @@ __device__ inline int sturm(const double *d, const double *e, int n, double x, d
     return c;
 }
 
-__global__ void k_bisect(const double *__restrict__ d, const double *__restrict__ e, int n,
-                         double *__restrict__ w, double *__restrict__ par) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Multisection: one wavefront per eigenvalue j; each round the 64 lanes count
+// eigenvalues below 64 interior points of [lo, hi] and the bracket shrinks to
+// the first sub-interval whose right end has more than j eigenvalues below it.
+__global__ void __launch_bounds__(256) k_bisect(const double *__restrict__ d, const double *__restrict__ e,
+                                                int n, double *__restrict__ w, double *__restrict__ par) {
+    const int lane = lane_id();
+    const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
-    double gl, gu, emax2;
-    gersh(d, e, n, gl, gu, emax2);
+    double gl = DBL_MAX, gu = -DBL_MAX, emax2 = 0.0;
+    for (int i = lane; i < n; i += kWave) {
+        const double el = i > 0 ? fabs(e[i - 1]) : 0.0;
+        const double er = i + 1 < n ? fabs(e[i]) : 0.0;
+        gl = fmin(gl, d[i] - el - er);
+        gu = fmax(gu, d[i] + el + er);
+        emax2 = fmax(emax2, er * er);
+    }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        gl = fmin(gl, __shfl_xor(gl, o, kWave));
+        gu = fmax(gu, __shfl_xor(gu, o, kWave));
+        emax2 = fmax(emax2, __shfl_xor(emax2, o, kWave));
+    }
     const double tnorm = fmax(fabs(gl), fabs(gu));
     const double pivmin = DBL_MIN * fmax(1.0, emax2);
     const double atol = 2.0 * kEps * tnorm + pivmin;
     double lo = gl - atol - 2.0 * kEps * tnorm, hi = gu + atol + 2.0 * kEps * tnorm;
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (hi - lo <= atol || mid <= lo || mid >= hi) break;
-        if (sturm(d, e, n, mid, pivmin) > j)
-            hi = mid;
-        else
-            lo = mid;
+    for (int round = 0; round < 64; ++round) {
+        if (hi - lo <= atol) break;
+        const double x = lo + (hi - lo) * ((double)(lane + 1) / (double)(kWave + 1));
+        const bool above = sturm(d, e, n, x, pivmin) > j;
+        const uint64_t mask = __ballot(above);
+        const double xprev = __shfl_up(x, 1, kWave);
+        if (mask == 0ull) {
+            const double xl = __shfl(x, kWave - 1, kWave);
+            if (!(xl > lo)) break;
+            lo = xl;
+        } else {
+            const int l = __ffsll((unsigned long long)mask) - 1;
+            const double xh = __shfl(x, l, kWave);
+            const double xlo = __shfl(xprev, l, kWave);
+            const double nlo = l > 0 ? xlo : lo;
+            if (!(xh < hi) && !(nlo > lo)) break;
+            hi = xh;
+            lo = nlo;
+        }
     }
-    w[j] = 0.5 * (lo + hi);
-    if (j == 0) {
-        par[0] = tnorm;
-        par[1] = pivmin;
+    if (lane == 0) {
+        w[j] = 0.5 * (lo + hi);
+        if (j == 0) {
+            par[0] = tnorm;
+            par[1] = pivmin;
+        }
     }
 }
 
@@ -187,14 +231,21 @@ __device__ inline double hash_unit(uint32_t a, uint32_t b) {
     return (double)h * (2.0 / 4294967296.0) - 1.0;
 }
 
-// Inverse iteration, one thread per eigenvector; arrays interleaved as a[i*n + j].
-__global__ void k_inviter(const double *__restrict__ d, const double *__restrict__ e, int n,
-                          const double *__restrict__ w, const double *__restrict__ par,
-                          double *__restrict__ dl, double *__restrict__ dd, double *__restrict__ du,
-                          double *__restrict__ du2, double *__restrict__ x, int *__restrict__ ipiv,
-                          double *__restrict__ Zv) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= n) return;
+// Inverse iteration: one wavefront per eigenvector with the LU factors of
+// T - lambda I in LDS; lane 0 runs the sequential factorization and solves, the
+// wavefront shares the vector operations.
+__global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, const double *__restrict__ e,
+                                                int n, const double *__restrict__ w,
+                                                const double *__restrict__ par, double *__restrict__ Zv) {
+    extern __shared__ double sm[];
+    double *dl = sm, *dd = sm + n, *du = sm + 2 * n, *du2 = sm + 3 * n, *x = sm + 4 * n;
+    int *ipiv = reinterpret_cast<int *>(sm + 5 * n);
+    const int j = blockIdx.x;
+    const int lane = lane_id();
+    if (n == 1) {
+        if (lane == 0) Zv[0] = 1.0;
+        return;
+    }
     const double tnorm = par[0];
     const double tight = kTightRel * tnorm;
     const double pert = 10.0 * kEps * fmax(tnorm, DBL_MIN);
@@ -202,73 +253,75 @@ __global__ void k_inviter(const double *__restrict__ d, const double *__restrict
     for (int i = j - 1; i >= 0 && w[i + 1] - w[i] <= tight; --i) ++pos;
     const double lam = w[j] + pert * pos;
     const double tiny = kEps * fmax(tnorm, DBL_MIN);
-#define IX(i) ((int64_t)(i) * n + j)
-    if (n == 1) {
-        Zv[0] = 1.0;
-        return;
+    for (int i = lane; i < n; i += kWave) {
+        dd[i] = d[i] - lam;
+        dl[i] = i + 1 < n ? e[i] : 0.0;
+        du[i] = i + 1 < n ? e[i] : 0.0;
+        du2[i] = 0.0;
+        x[i] = hash_unit((uint32_t)i, (uint32_t)j);
     }
-    for (int i = 0; i < n; ++i) dd[IX(i)] = d[i] - lam;
-    for (int i = 0; i + 1 < n; ++i) {
-        dl[IX(i)] = e[i];
-        du[IX(i)] = e[i];
-    }
-    for (int i = 0; i + 2 < n; ++i) du2[IX(i)] = 0.0;
-    // LU with partial pivoting of the tridiagonal T - lam I
-    for (int i = 0; i + 1 < n; ++i) {
-        const double a = dd[IX(i)], b = dl[IX(i)];
-        if (fabs(a) >= fabs(b)) {
-            ipiv[IX(i)] = i;
-            const double piv = a != 0.0 ? a : tiny;
-            dd[IX(i)] = piv;
-            const double f = b / piv;
-            dl[IX(i)] = f;
-            dd[IX(i + 1)] -= f * du[IX(i)];
-        } else {
-            ipiv[IX(i)] = i + 1;
-            const double f = a / b;
-            dd[IX(i)] = b;
-            dl[IX(i)] = f;
-            const double tmp = du[IX(i)];
-            du[IX(i)] = dd[IX(i + 1)];
-            dd[IX(i + 1)] = tmp - f * dd[IX(i + 1)];
-            if (i + 2 < n) {
-                du2[IX(i)] = du[IX(i + 1)];
-                du[IX(i + 1)] = -f * du[IX(i + 1)];
-            }
-        }
-    }
-    if (dd[IX(n - 1)] == 0.0) dd[IX(n - 1)] = tiny;
-    for (int i = 0; i < n; ++i) x[IX(i)] = hash_unit((uint32_t)i, (uint32_t)j);
-    for (int it = 0; it < 3; ++it) {
-        // forward: apply the row interchanges and L
+    __syncthreads();
+    if (lane == 0) {
+        // LU with partial pivoting of the tridiagonal T - lam I
         for (int i = 0; i + 1 < n; ++i) {
-            const double f = dl[IX(i)];
-            if (ipiv[IX(i)] == i) {
-                x[IX(i + 1)] -= f * x[IX(i)];
+            const double a = dd[i], b = dl[i];
+            if (fabs(a) >= fabs(b)) {
+                ipiv[i] = i;
+                const double piv = a != 0.0 ? a : tiny;
+                dd[i] = piv;
+                const double f = b / piv;
+                dl[i] = f;
+                dd[i + 1] -= f * du[i];
             } else {
-                const double t0 = x[IX(i)];
-                x[IX(i)] = x[IX(i + 1)];
-                x[IX(i + 1)] = t0 - f * x[IX(i)];
+                ipiv[i] = i + 1;
+                const double f = a / b;
+                dd[i] = b;
+                dl[i] = f;
+                const double tmp = du[i];
+                du[i] = dd[i + 1];
+                dd[i + 1] = tmp - f * dd[i + 1];
+                if (i + 2 < n) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
             }
         }
-        // back substitution with U (diagonal dd, super-diagonals du, du2)
-        x[IX(n - 1)] /= dd[IX(n - 1)];
-        x[IX(n - 2)] = (x[IX(n - 2)] - du[IX(n - 2)] * x[IX(n - 1)]) / dd[IX(n - 2)];
-        for (int i = n - 3; i >= 0; --i)
-            x[IX(i)] = (x[IX(i)] - du[IX(i)] * x[IX(i + 1)] - du2[IX(i)] * x[IX(i + 2)]) / dd[IX(i)];
+        if (dd[n - 1] == 0.0) dd[n - 1] = tiny;
+    }
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+        if (lane == 0) {
+            for (int i = 0; i + 1 < n; ++i) {
+                const double f = dl[i];
+                if (ipiv[i] == i) {
+                    x[i + 1] -= f * x[i];
+                } else {
+                    const double t0 = x[i];
+                    x[i] = x[i + 1];
+                    x[i + 1] = t0 - f * x[i];
+                }
+            }
+            x[n - 1] /= dd[n - 1];
+            x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
+            for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+        }
+        __syncthreads();
         double mx = 0.0;
-        for (int i = 0; i < n; ++i) mx = fmax(mx, fabs(x[IX(i)]));
+        for (int i = lane; i < n; i += kWave) mx = fmax(mx, fabs(x[i]));
+#pragma unroll
+        for (int o = kWave / 2; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, kWave));
         const double sc = mx > 0.0 ? 1.0 / mx : 1.0;
         double s2 = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const double v = x[IX(i)] * sc;
+        for (int i = lane; i < n; i += kWave) {
+            const double v = x[i] * sc;
             s2 += v * v;
         }
+        s2 = wave_sum(s2);
         const double nr = sc / sqrt(s2);
-        for (int i = 0; i < n; ++i) x[IX(i)] *= nr;
+        for (int i = lane; i < n; i += kWave) x[i] *= nr;
+        __syncthreads();
     }
-    for (int i = 0; i < n; ++i) Zv[(int64_t)j * n + i] = x[IX(i)];
-#undef IX
+    for (int i = lane; i < n; i += kWave) Zv[(int64_t)j * n + i] = x[i];
 }
 
 // Modified Gram-Schmidt (two passes) inside clusters with gaps below the tight threshold.
@@ -317,22 +370,29 @@ __global__ void __launch_bounds__(256) k_backtransform(const double *__restrict_
         const int i = lane + t * kWave;
         z[t] = (t < tpl && i < n) ? Zv[(int64_t)j * n + i] : 0.0;
     }
+    double vc[kTpl], vn[kTpl];
+    auto load_v = [&](int k, double (&dst)[kTpl]) {
+        const double *vk = Vh + (int64_t)k * n - (k + 1);  // vk[i] for i in [k+1, n)
+#pragma unroll
+        for (int t = 0; t < kTpl; ++t) {
+            const int i = lane + t * kWave;
+            dst[t] = (t < tpl && i > k && i < n) ? vk[i] : 0.0;
+        }
+    };
+    if (n >= 3) load_v(n - 3, vc);
     for (int k = n - 3; k >= 0; --k) {
         const double tk = tau[k];
-        if (tk == 0.0) continue;
-        const double *vk = Vh + (int64_t)k * n - (k + 1);  // vk[i] for i in [k+1, n)
-        double dot = 0.0;
+        if (k > 0) load_v(k - 1, vn);
+        if (tk != 0.0) {
+            double dot = 0.0;
 #pragma unroll
-        for (int t = 0; t < kTpl; ++t) {
-            const int i = lane + t * kWave;
-            if (t < tpl && i > k && i < n) dot += vk[i] * z[t];
-        }
-        const double s = tk * wave_sum(dot);
+            for (int t = 0; t < kTpl; ++t) dot += vc[t] * z[t];
+            const double sfac = tk * wave_sum(dot);
 #pragma unroll
-        for (int t = 0; t < kTpl; ++t) {
-            const int i = lane + t * kWave;
-            if (t < tpl && i > k && i < n) z[t] -= s * vk[i];
+            for (int t = 0; t < kTpl; ++t) z[t] -= sfac * vc[t];
         }
+#pragma unroll
+        for (int t = 0; t < kTpl; ++t) vc[t] = vn[t];
     }
 #pragma unroll
     for (int t = 0; t < kTpl; ++t) {
@@ -372,31 +432,26 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
     EigWs s = eig_layout(a, n);
-    hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(1024), 0, st, H, ldh, n, s.A, s.Vh, s.d, s.e, s.tau);
+    if (n <= kLdsMaxN)
+        hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(512), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
+    else
+        hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(512), 0, st, H, ldh, n, s.A, s.Vh, s.d, s.e, s.tau);
     CD_LAUNCH_CHECK();
     const unsigned g64 = (unsigned)ceil_div(n, 64);
-    hipLaunchKernelGGL(k_bisect, dim3(g64), dim3(64), 0, st, s.d, s.e, n, s.w, s.par);
+    hipLaunchKernelGGL(k_bisect, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, s.d, s.e, n, s.w, s.par);
     CD_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_inviter, dim3(g64), dim3(64), 0, st, s.d, s.e, n, s.w, s.par, s.dl, s.dd,
-                       s.du, s.du2, s.x, s.ipiv, s.Zv);
+    const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n;
+    hipLaunchKernelGGL(k_inviter, dim3(n), dim3(64), inv_lds, st, s.d, s.e, n, s.w, s.par, s.Zv);
     CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cluster_mgs, dim3(n), dim3(256), 0, st, s.w, s.par, n, s.Zv);
     CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_backtransform, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, s.Vh, s.tau,
-                       s.Zv, n, Y, ldy);
+                       s.Zv, n, s.T, n);
     CD_LAUNCH_CHECK();
-    // two Newton-Schulz steps: T = Y B1, Y = T B2
+    // one Newton-Schulz step Y = T (3 I - T^T T)/2: inverse-iteration vectors of
+    // eigenvalues further apart than the tight-cluster threshold are orthogonal
+    // to about 1e-10, so one step brings the defect to rounding level
     const unsigned gnn = (unsigned)ceil_div((int64_t)n * n, 256);
-    {
-        Seg2 sy;
-        sy.X1 = Y;
-        sy.ld1 = ldy;
-        sy.p1 = n;
-        CD_TRY(gram(sy, Y, ldy, n, n, s.G, n, s.part, st));
-        hipLaunchKernelGGL(k_ns_prep, dim3(gnn), dim3(256), 0, st, s.G, n, s.Bm);
-        CD_LAUNCH_CHECK();
-        CD_TRY(update(sy, s.Bm, n, 1.0, 0.0, s.T, n, n, n, st));
-    }
     {
         Seg2 stt;
         stt.X1 = s.T;

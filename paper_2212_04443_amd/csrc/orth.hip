@@ -13,8 +13,9 @@
 //             1e-13 (then it lies, to working accuracy, in the span of the
 //             columns before it).  Dependent columns are replaced by Philox
 //             columns and everything is redone.
-//   BCGS      one more pass against V (R^{-1} may amplify the remaining
-//             non-orthogonality to V), then a second, plain CholQR.
+//   BCGS      one more pass against V when the smallest scaled pivot is below
+//             0.01 (R^{-1} may then amplify the remaining non-orthogonality to
+//             V above rounding level), then a second, plain CholQR.
 #include <vector>
 
 #include "device_util.h"
@@ -34,7 +35,7 @@ OrthWs orth_layout(Arena &a, int64_t n, int ksub, int kb) {
     s.G = a.take<double>((size_t)kb * kb);
     s.Rinv = a.take<double>((size_t)kb * kb);
     s.norm0 = a.take<double>(kb);
-    s.dep = a.take<int>(kb + 1);
+    s.dep = a.take<int>(kb + 2);
     size_t pe = std::max(gram_partial_elems(n, std::max(ksub, 1), kb), gram_partial_elems(n, kb, kb));
     pe = std::max(pe, colnorm_partial_elems(n, kb));
     s.part = a.take<double>(pe);
@@ -72,7 +73,7 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
     const OrthWs s = orth_layout(a, n, V.cols(), kb);
-    int *hdep = static_cast<int *>(pinned_host(sizeof(int) * (kb + 1), 2));
+    int *hdep = static_cast<int *>(pinned_host(sizeof(int) * (kb + 2), 2));
     if (!hdep) return fail(CHEBDAV_ENOMEM, "pinned host allocation failed");
     Seg2 xs;
     xs.X1 = X;
@@ -85,7 +86,7 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
         CD_TRY(project_out(V, X, ldx, kb, n, s, st));
         CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
         CD_TRY(chol_rinv(s.G, kb, s.norm0, s.Rinv, s.dep, 1, st));
-        CD_HIP(hipMemcpyAsync(hdep, s.dep, sizeof(int) * (kb + 1), hipMemcpyDeviceToHost, st));
+        CD_HIP(hipMemcpyAsync(hdep, s.dep, sizeof(int) * (kb + 2), hipMemcpyDeviceToHost, st));
         CD_HIP(hipStreamSynchronize(st));
         if (!hdep[kb]) break;
         if (attempt == 3) return fail(CHEBDAV_EBREAKDOWN, "dependent vectors persist after 3 replacement rounds");
@@ -100,7 +101,9 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
         }
     }
     CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
-    CD_TRY(project_out(V, X, ldx, kb, n, s, st));
+    // a third projection only when R^{-1} can have amplified the remaining
+    // components along V above rounding level (smallest scaled pivot < 0.01)
+    if (hdep[kb + 1]) CD_TRY(project_out(V, X, ldx, kb, n, s, st));
     CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
     CD_TRY(chol_rinv(s.G, kb, nullptr, s.Rinv, s.dep, 0, st));
     CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));

@@ -15,16 +15,18 @@ constexpr int kMaxKb = 64;
 //     dependent on the ones before it.  Rinv = S Rt^{-1}, so X Rinv has
 //     orthonormal columns.
 //   scaled = 0: plain G = R^T R, Rinv = R^{-1}; a non-positive pivot sets dep[kb].
-// dep[j] (j < kb) = 1 for dependent columns, dep[kb] = 1 if any.
+// dep[j] (j < kb) = 1 for dependent columns, dep[kb] = 1 if any, dep[kb+1] = 1 if
+// the smallest diagonal entry of the (scaled) factor is below 0.01, i.e. R^{-1}
+// may amplify the block's residual components along the basis by more than 100.
 __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G, int kb,
                                                    const double *__restrict__ norm0,
                                                    double *__restrict__ Rinv, int *__restrict__ dep,
                                                    int scaled) {
     __shared__ double A[kMaxKb][kMaxKb + 1];
     __shared__ double s[kMaxKb];
-    __shared__ int d[kMaxKb + 1];
+    __shared__ int d[kMaxKb + 2];
     const int tid = threadIdx.x;
-    if (tid <= kb) d[tid] = 0;
+    if (tid <= kb + 1) d[tid] = 0;
     __syncthreads();
     if (tid < kb) {
         if (scaled) {
@@ -82,11 +84,16 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
     __syncthreads();
     if (tid == 0) {
         int any = 0;
-        for (int j = 0; j < kb; ++j) any |= d[j];
+        double rmin = 1.0;
+        for (int j = 0; j < kb; ++j) {
+            any |= d[j];
+            if (!d[j]) rmin = fmin(rmin, A[j][j]);
+        }
         d[kb] = any;
+        d[kb + 1] = rmin < 0.01;
     }
     __syncthreads();
-    if (tid <= kb) dep[tid] = d[tid];
+    if (tid <= kb + 1) dep[tid] = d[tid];
 }
 
 __global__ void k_h_insert(double *__restrict__ H, int64_t ldh, const double *__restrict__ C, int k,

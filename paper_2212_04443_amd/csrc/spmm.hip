@@ -51,6 +51,17 @@ __device__ inline void load_vec(const T *p, T (&v)[VE]) {
     __builtin_memcpy(v, &x, sizeof(VT));
 }
 
+// Neighbour chunk: CH column indices per group per round (each lane of the group
+// holds CH/G of them); all CH neighbour rows of a chunk are requested before any
+// is consumed, the next chunk's indices are requested before this chunk's rows,
+// and the row's own U and Z entries are requested before the neighbour loop.
+template <int G>
+struct Chunk {
+    static constexpr int CH = G >= 16 ? G : 16;
+    static constexpr int PER = CH / G;
+    static constexpr int UNR = CH < 8 ? CH : 8;
+};
+
 template <typename T, typename TO, int VE, int G>
 __global__ void __launch_bounds__(kBlock)
     k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -58,6 +69,7 @@ __global__ void __launch_bounds__(kBlock)
                 int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
                 int w) {
     constexpr int GPB = kBlock / G;  // rows per block
+    constexpr int CH = Chunk<G>::CH, PER = Chunk<G>::PER, UNR = Chunk<G>::UNR;
     const int lane = lane_id();
     const int gl = lane & (G - 1);
     // XCD-aware renumbering: gridDim.x is a multiple of 8; consecutive hardware
@@ -71,61 +83,58 @@ __global__ void __launch_bounds__(kBlock)
     const bool active = c0 < w;
     const int64_t beg = row_ptr[r], end = row_ptr[r + 1];
 
-    T acc[VE];
-#pragma unroll
-    for (int e = 0; e < VE; ++e) acc[e] = T(0);
-
-    for (int64_t base = beg; base < end; base += G) {
-        const int64_t idx = base + gl;
-        int jl = 0;
-        T dl = T(0);
-        if (idx < end) {
-            jl = col[idx];
-            dl = dinv[jl];
-        }
-        const int cnt = (int)min<int64_t>(G, end - base);
-        int t = 0;
-        for (; t + 4 <= cnt; t += 4) {
-            const int j0 = __shfl(jl, t + 0, G), j1 = __shfl(jl, t + 1, G);
-            const int j2 = __shfl(jl, t + 2, G), j3 = __shfl(jl, t + 3, G);
-            const T d0 = __shfl(dl, t + 0, G), d1 = __shfl(dl, t + 1, G);
-            const T d2 = __shfl(dl, t + 2, G), d3 = __shfl(dl, t + 3, G);
-            if (active) {
-                T u0[VE], u1[VE], u2[VE], u3[VE];
-                load_vec<T, VE>(U + (int64_t)j0 * ldu + c0, u0);
-                load_vec<T, VE>(U + (int64_t)j1 * ldu + c0, u1);
-                load_vec<T, VE>(U + (int64_t)j2 * ldu + c0, u2);
-                load_vec<T, VE>(U + (int64_t)j3 * ldu + c0, u3);
-#pragma unroll
-                for (int e = 0; e < VE; ++e) {
-                    acc[e] += d0 * u0[e];
-                    acc[e] += d1 * u1[e];
-                    acc[e] += d2 * u2[e];
-                    acc[e] += d3 * u3[e];
-                }
-            }
-        }
-        for (; t < cnt; ++t) {
-            const int j0 = __shfl(jl, t, G);
-            const T d0 = __shfl(dl, t, G);
-            if (active) {
-                T u0[VE];
-                load_vec<T, VE>(U + (int64_t)j0 * ldu + c0, u0);
-#pragma unroll
-                for (int e = 0; e < VE; ++e) acc[e] += d0 * u0[e];
-            }
-        }
-    }
-    if (!active) return;
-    const T di = dinv[r];
-    T ur[VE], zr[VE];
+    T ur[VE], zr[VE], acc[VE];
 #pragma unroll
     for (int e = 0; e < VE; ++e) {
         ur[e] = T(0);
         zr[e] = T(0);
+        acc[e] = T(0);
     }
-    if (beta != T(0)) load_vec<T, VE>(U + r * ldu + c0, ur);
-    if (Z != nullptr) load_vec<T, VE>(Z + r * ldz + c0, zr);
+    if (active && beta != T(0)) load_vec<T, VE>(U + r * ldu + c0, ur);
+    if (active && Z != nullptr) load_vec<T, VE>(Z + r * ldz + c0, zr);
+    const T di = dinv[r];
+
+    int jl[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t idx = beg + gl + (int64_t)k * G;
+        jl[k] = idx < end ? col[idx] : 0;
+    }
+    for (int64_t base = beg; base < end; base += CH) {
+        const int cnt = (int)min<int64_t>(CH, end - base);
+        int jn[PER];
+        T dl[PER];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int64_t nidx = base + CH + gl + (int64_t)k * G;
+            jn[k] = nidx < end ? col[nidx] : 0;
+            dl[k] = (base + gl + (int64_t)k * G) < end ? dinv[jl[k]] : T(0);
+        }
+        for (int t0 = 0; t0 < cnt; t0 += UNR) {
+            T u[UNR][VE];
+#pragma unroll
+            for (int i = 0; i < UNR; ++i) {
+                const int t = t0 + i;
+                const int j = __shfl(jl[(t / G) % PER], t % G, G);
+                if (active && t < cnt) {
+                    load_vec<T, VE>(U + (int64_t)j * ldu + c0, u[i]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) u[i][e] = T(0);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < UNR; ++i) {
+                const int t = t0 + i;
+                const T dj = __shfl(dl[(t / G) % PER], t % G, G);
+#pragma unroll
+                for (int e = 0; e < VE; ++e) acc[e] += dj * u[i][e];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < PER; ++k) jl[k] = jn[k];
+    }
+    if (!active) return;
     TO *yp = Y + r * ldy + c0;
     if constexpr (sizeof(TO) == sizeof(T)) {
         T y[VE];
