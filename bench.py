@@ -78,6 +78,28 @@ def run_forms(cd, torch, g, cfg, forms, steps, warmup, seed):
     return out
 
 
+def warm_start_form(cd, torch, g, cfg, steps, seed):
+    """Solve started from the trained network (inference + Rayleigh-Ritz included)."""
+    from paper_2212_04443_amd import gcn
+    if not os.path.exists(gcn.WEIGHTS_FILE):
+        return None
+    net = gcn.Net.load()
+    p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed)
+    ws = torch.empty(cd.solve_workspace_size(g, p), dtype=torch.uint8, device="cuda")
+    V0, _ = gcn.warm_start(g, net, seed=seed)
+    cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        V0, _ = gcn.warm_start(g, net, seed=seed)
+        r = cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    log("form gcn-warm: %.2f ms/solve (inference included), %d iterations" % (1e3 * t, r.stats["iterations"]))
+    return dict(seconds=t, iterations=r.stats["iterations"], n_spmm_filter=r.stats["n_spmm_filter"],
+                max_residual=r.stats["max_residual"], evals=r.evals.cpu().numpy())
+
+
 def measured_traffic(workload):
     """HBM bytes per k_cheb_step launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a plain
@@ -211,6 +233,10 @@ def main():
     if len(forms) > 1:
         a, b2 = res[forms[0]]["evals"], res[forms[1]]["evals"]
         line["forms_max_dlambda"] = float(np.abs(a - b2).max())
+    ws_form = warm_start_form(cd, torch, g, cfg, args.steps, args.seed)
+    if ws_form is not None:
+        line["forms"]["gcn_warm_f64"] = {k: v for k, v in ws_form.items() if k != "evals"}
+        line["gcn_warm_max_dlambda"] = float(np.abs(ws_form["evals"] - prim["evals"]).max())
     if not args.no_cpu_baseline:
         log("running the CPU oracle on the same workload ...")
         cb, ref = cpu_baseline(edges, n, cfg, args.seed)

@@ -194,6 +194,64 @@ chebdav_status chebdav_solve(const chebdav_graph *g, const chebdav_params *p,
                              void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Learned warm start (not in the paper): a three-layer graph-convolution
+ * network whose output block, after Rayleigh-Ritz, is passed to chebdav_solve
+ * as V_init (the progressive-filtering interface of Alg. 2 steps 2 and 17).
+ *
+ *   Z_l = Ahat (H_{l-1} W_l), H_l = ReLU(Z_l) for l = 1, 2; out = Z_3;
+ *   Ahat = D^{-1/2} S D^{-1/2};  H_0 = X0.
+ *
+ * dims[4] = {d0, d1, d2, d3}: input width and the three layer widths (each in
+ * [1, 256]).  W[l]: device float, dims[l] x dims[l+1], row-major.  X0: device
+ * float n x d0.  acts: device float, caller-owned, n x (d1 + d2): H_1 then H_2,
+ * written by forward and read by backward.  out / d_out: device float n x d3.
+ * dW[l]: device float, same shapes as W[l] (overwritten).  All FP32; gradient
+ * sums over nodes are split in a fixed way and added in FP64 (deterministic).
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_gcn_workspace_size(const chebdav_graph *g, const int dims[4], size_t *bytes);
+chebdav_status chebdav_gcn_forward(const chebdav_graph *g, const int dims[4], const float *X0,
+                                   const float *const W[3], float *acts, float *out, void *workspace,
+                                   size_t ws_bytes, void *hip_stream);
+chebdav_status chebdav_gcn_backward(const chebdav_graph *g, const int dims[4], const float *X0,
+                                    const float *const W[3], const float *acts, const float *d_out,
+                                    float *const dW[3], void *workspace, size_t ws_bytes,
+                                    void *hip_stream);
+
+/* Input features X (device float, n x (n_gauss + 1), leading dimension ldx):
+ * n_gauss standard normal channels (Box-Muller on Philox4x32-10, key = seed,
+ * counter (row, row >> 32, channel pair, 1)) and sqrt(deg_i / mean degree). */
+chebdav_status chebdav_gcn_features(const chebdav_graph *g, uint64_t seed, int n_gauss, float *X,
+                                    int64_t ldx, void *hip_stream);
+
+/* Rotation- and sign-invariant subspace loss against orthonormal targets U
+ * (device double, n x ku, ldu):  L = 1 - tr(U^T X (X^T X)^{-1} X^T U) / ku, and
+ * dL/dX (device float, n x kx, lddx; NULL to skip).  X: device float n x kx.
+ * loss: host.  kx, ku <= 64.  EBREAKDOWN if X^T X is not positive definite.
+ * Synchronizes the stream. */
+chebdav_status chebdav_subspace_loss_workspace_size(int64_t n, int kx, int ku, size_t *bytes);
+chebdav_status chebdav_subspace_loss(const float *X, int64_t ldx, const double *U, int64_t ldu,
+                                     int64_t n, int kx, int ku, double *loss, float *dX,
+                                     int64_t lddx, void *workspace, size_t ws_bytes,
+                                     void *hip_stream);
+
+/* One Adam step (Kingma & Ba) on count parameters (device float arrays):
+ * m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
+ * w <- w - lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).  step >= 1. */
+chebdav_status chebdav_adam_step(float *params, const float *grads, float *m, float *v, int64_t count,
+                                 double lr, double beta1, double beta2, double eps, int step,
+                                 void *hip_stream);
+
+/* Rayleigh-Ritz of span(X) (X: device float, n x k, ldx; k <= 64): X is
+ * orthonormalized (as chebdav_orthonormalize, Philox key = seed), then V (device
+ * double, n x k, ldv) receives the Ritz vectors of A in ascending order of
+ * their Rayleigh quotients, written to ritz (device double[k]).  This is the
+ * ordering progressive filtering assumes for V_init.  Synchronizes the stream. */
+chebdav_status chebdav_rayleigh_ritz_workspace_size(const chebdav_graph *g, int k, size_t *bytes);
+chebdav_status chebdav_rayleigh_ritz(const chebdav_graph *g, const float *X, int64_t ldx, int k,
+                                     uint64_t seed, double *V, int64_t ldv, double *ritz,
+                                     void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Building blocks exposed for verification.
  * ------------------------------------------------------------------------ */
 /* Symmetric eigendecomposition of the n x n matrix H (device double, row-major,

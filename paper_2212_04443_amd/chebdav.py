@@ -32,6 +32,9 @@ EXPORTED = [
     "chebdav_orthonormalize_workspace_size", "chebdav_orthonormalize",
     "chebdav_solve_workspace_size", "chebdav_solve", "chebdav_small_eig_workspace_size",
     "chebdav_small_eig", "chebdav_philox_fill", "chebdav_dinv", "chebdav_last_error",
+    "chebdav_gcn_workspace_size", "chebdav_gcn_forward", "chebdav_gcn_backward", "chebdav_gcn_features",
+    "chebdav_subspace_loss_workspace_size", "chebdav_subspace_loss", "chebdav_adam_step",
+    "chebdav_rayleigh_ritz_workspace_size", "chebdav_rayleigh_ritz",
 ]
 
 
@@ -86,6 +89,15 @@ def _load():
         "chebdav_small_eig": [p, i64, i32, p, p, i64, p, sz, p],
         "chebdav_philox_fill": [p, i64, i32, i64, u64, u64, p],
         "chebdav_dinv": [p, p, i64, p],
+        "chebdav_gcn_workspace_size": [p, P(i32), P(sz)],
+        "chebdav_gcn_forward": [p, P(i32), p, P(p), p, p, p, sz, p],
+        "chebdav_gcn_backward": [p, P(i32), p, P(p), p, p, P(p), p, sz, p],
+        "chebdav_gcn_features": [p, u64, i32, p, i64, p],
+        "chebdav_subspace_loss_workspace_size": [i64, i32, i32, P(sz)],
+        "chebdav_subspace_loss": [p, i64, p, i64, i64, i32, i32, P(d), p, i64, p, sz, p],
+        "chebdav_adam_step": [p, p, p, p, i64, d, d, d, d, i32, p],
+        "chebdav_rayleigh_ritz_workspace_size": [p, i32, P(sz)],
+        "chebdav_rayleigh_ritz": [p, p, i64, i32, u64, p, i64, p, p, sz, p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -301,3 +313,81 @@ def dinv(deg: torch.Tensor, stream=None) -> torch.Tensor:
     out = torch.empty(deg.shape[0], dtype=torch.float64, device=deg.device)
     _check(_lib.chebdav_dinv(_ptr(deg), _ptr(out), deg.shape[0], _stream(stream)))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Learned warm start (graph-convolution network) building blocks
+# ---------------------------------------------------------------------------
+def _dims(dims):
+    return (ctypes.c_int * 4)(*[int(x) for x in dims])
+
+
+def _ptr_array(ts):
+    return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+
+def gcn_workspace(g: Graph, dims) -> torch.Tensor:
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_gcn_workspace_size(g.handle, _dims(dims), ctypes.byref(nb)))
+    return _workspace(nb.value, g.device)
+
+
+def gcn_forward(g: Graph, dims, X0: torch.Tensor, W, acts=None, out=None, workspace=None, stream=None):
+    """chebdav_gcn_forward.  W: three float32 tensors (d_l x d_{l+1}).  Returns (out, acts)."""
+    n = g.n
+    if acts is None:
+        acts = torch.empty(n * (dims[1] + dims[2]), dtype=torch.float32, device=g.device)
+    if out is None:
+        out = torch.empty(n, dims[3], dtype=torch.float32, device=g.device)
+    ws = workspace if workspace is not None else gcn_workspace(g, dims)
+    _check(_lib.chebdav_gcn_forward(g.handle, _dims(dims), _ptr(X0), _ptr_array(W), _ptr(acts), _ptr(out),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+    return out, acts
+
+
+def gcn_backward(g: Graph, dims, X0, W, acts, d_out, dW=None, workspace=None, stream=None):
+    """chebdav_gcn_backward.  Returns the three weight gradients."""
+    if dW is None:
+        dW = [torch.empty_like(w) for w in W]
+    ws = workspace if workspace is not None else gcn_workspace(g, dims)
+    _check(_lib.chebdav_gcn_backward(g.handle, _dims(dims), _ptr(X0), _ptr_array(W), _ptr(acts), _ptr(d_out),
+                                     _ptr_array(dW), _ptr(ws), ws.numel(), _stream(stream)))
+    return dW
+
+
+def gcn_features(g: Graph, seed: int, n_gauss: int = 16, stream=None) -> torch.Tensor:
+    X = torch.empty(g.n, n_gauss + 1, dtype=torch.float32, device=g.device)
+    _check(_lib.chebdav_gcn_features(g.handle, seed, n_gauss, _ptr(X), n_gauss + 1, _stream(stream)))
+    return X
+
+
+def subspace_loss(X: torch.Tensor, U: torch.Tensor, grad: bool = True, workspace=None, stream=None):
+    """chebdav_subspace_loss: (loss, dL/dX or None)."""
+    n, kx = X.shape
+    ku = U.shape[1]
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_subspace_loss_workspace_size(n, kx, ku, ctypes.byref(nb)))
+    ws = workspace if workspace is not None and workspace.numel() >= nb.value else _workspace(nb.value, X.device)
+    dX = torch.empty_like(X) if grad else None
+    loss = ctypes.c_double()
+    _check(_lib.chebdav_subspace_loss(_ptr(X), _ld(X), _ptr(U), _ld(U), n, kx, ku, ctypes.byref(loss),
+                                      _ptr(dX), _ld(dX) if grad else kx, _ptr(ws), ws.numel(), _stream(stream)))
+    return loss.value, dX
+
+
+def adam_step(params, grads, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1, stream=None):
+    _check(_lib.chebdav_adam_step(_ptr(params), _ptr(grads), _ptr(m), _ptr(v), params.numel(), lr, beta1, beta2,
+                                  eps, step, _stream(stream)))
+
+
+def rayleigh_ritz(g: Graph, X: torch.Tensor, seed: int = 0, stream=None):
+    """chebdav_rayleigh_ritz: (V float64 n x k, ritz values ascending)."""
+    n, k = X.shape
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_rayleigh_ritz_workspace_size(g.handle, k, ctypes.byref(nb)))
+    ws = _workspace(nb.value, X.device)
+    V = torch.empty(n, k, dtype=torch.float64, device=X.device)
+    ritz = torch.empty(k, dtype=torch.float64, device=X.device)
+    _check(_lib.chebdav_rayleigh_ritz(g.handle, _ptr(X), _ld(X), k, seed, _ptr(V), _ld(V), _ptr(ritz), _ptr(ws),
+                                      ws.numel(), _stream(stream)))
+    return V, ritz

@@ -212,6 +212,74 @@ chebdav_status chebdav_dinv(const int32_t *deg, double *dinv, int64_t n, void *h
     return dinv_table(deg, dinv, n, as_stream(hip_stream));
 }
 
+chebdav_status chebdav_gcn_workspace_size(const chebdav_graph *gh, const int dims[4], size_t *bytes) {
+    CHECK_GRAPH(gh);
+    if (!dims || !bytes) return fail(CHEBDAV_EINVAL, "NULL argument");
+    *bytes = gcn_ws_bytes(gh->g->n, dims);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_gcn_features(const chebdav_graph *gh, uint64_t seed, int n_gauss, float *X, int64_t ldx,
+                                    void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!X) return fail(CHEBDAV_EINVAL, "X is NULL");
+    return gcn_features(gh->g, seed, n_gauss, X, ldx, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_gcn_forward(const chebdav_graph *gh, const int dims[4], const float *X0,
+                                   const float *const W[3], float *acts, float *out, void *workspace,
+                                   size_t ws_bytes, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!dims || !X0 || !W || !W[0] || !W[1] || !W[2] || !acts || !out) return fail(CHEBDAV_EINVAL, "NULL argument");
+    return gcn_forward(gh->g, dims, X0, W, acts, out, workspace, ws_bytes, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_gcn_backward(const chebdav_graph *gh, const int dims[4], const float *X0,
+                                    const float *const W[3], const float *acts, const float *d_out,
+                                    float *const dW[3], void *workspace, size_t ws_bytes, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!dims || !X0 || !W || !acts || !d_out || !dW || !dW[0] || !dW[1] || !dW[2])
+        return fail(CHEBDAV_EINVAL, "NULL argument");
+    return gcn_backward(gh->g, dims, X0, W, acts, d_out, dW, workspace, ws_bytes, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_subspace_loss_workspace_size(int64_t n, int kx, int ku, size_t *bytes) {
+    if (!bytes || n < 1 || kx < 1 || ku < 1) return fail(CHEBDAV_EINVAL, "bad arguments");
+    *bytes = loss_ws_bytes(n, kx, ku);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_subspace_loss(const float *X, int64_t ldx, const double *U, int64_t ldu, int64_t n, int kx,
+                                     int ku, double *loss, float *dX, int64_t lddx, void *workspace,
+                                     size_t ws_bytes, void *hip_stream) {
+    if (!X || !U || ldx < kx || ldu < ku || (dX && lddx < kx)) return fail(CHEBDAV_EINVAL, "bad arguments");
+    return subspace_loss(X, ldx, U, ldu, n, kx, ku, loss, dX, lddx, workspace, ws_bytes, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_adam_step(float *params, const float *grads, float *m, float *v, int64_t count, double lr,
+                                 double beta1, double beta2, double eps, int step, void *hip_stream) {
+    if (count > 0 && (!params || !grads || !m || !v)) return fail(CHEBDAV_EINVAL, "NULL argument");
+    return adam_step(params, grads, m, v, count, lr, beta1, beta2, eps, step, as_stream(hip_stream));
+}
+
+chebdav_status chebdav_rayleigh_ritz_workspace_size(const chebdav_graph *gh, int k, size_t *bytes) {
+    CHECK_GRAPH(gh);
+    if (!bytes || k < 1) return fail(CHEBDAV_EINVAL, "bad arguments");
+    *bytes = rr_ws_bytes(gh->g->n, k);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_rayleigh_ritz(const chebdav_graph *gh, const float *X, int64_t ldx, int k, uint64_t seed,
+                                     double *V, int64_t ldv, double *ritz, void *workspace, size_t ws_bytes,
+                                     void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!X || !V || !ritz || ldx < k || ldv < k) return fail(CHEBDAV_EINVAL, "bad arguments");
+    hipStream_t st = as_stream(hip_stream);
+    CD_TRY(rayleigh_ritz(gh->g, X, ldx, k, seed, V, ldv, ritz, workspace, ws_bytes, st));
+    CD_HIP(hipStreamSynchronize(st));
+    return CHEBDAV_OK;
+}
+
 const char *chebdav_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

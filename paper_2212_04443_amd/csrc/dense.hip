@@ -243,27 +243,6 @@ __global__ void k_fill(double *__restrict__ p, int64_t count, double v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += stride) p[e] = v;
 }
 
-// Philox4x32-10 (Salmon et al. 2011).
-__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
-#pragma unroll
-    for (int rnd = 0; rnd < 10; ++rnd) {
-        if (rnd > 0) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)M0 * c[0];
-        const uint64_t p1 = (uint64_t)M1 * c[2];
-        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
-        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-    }
-}
-
 __global__ void k_philox(double *__restrict__ X, int64_t n, int w, int64_t ld, uint64_t seed,
                          uint64_t first_col) {
     const int64_t total = n * (int64_t)w;
@@ -273,7 +252,7 @@ __global__ void k_philox(double *__restrict__ X, int64_t n, int w, int64_t ld, u
         const int j = (int)(e - r * w);
         const uint64_t q = first_col + (uint64_t)j;
         uint32_t c[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32), (uint32_t)q, 0u};
-        philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+        philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
         const uint64_t u = (((uint64_t)c[1] << 32) | c[0]) >> 11;
         X[r * ld + j] = (double)u * 0x1.0p-52 - 1.0;
     }

@@ -158,4 +158,21 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
                               uint64_t seed, uint64_t *next_col, int *n_replaced, void *ws,
                               size_t ws_bytes, hipStream_t st);
 
+// ---- gcn.hip (learned warm start)
+size_t gcn_ws_bytes(int64_t n, const int dims[4]);
+chebdav_status gcn_forward(const Graph *g, const int dims[4], const float *X0, const float *const W[3], float *acts,
+                           float *out, void *ws, size_t ws_bytes, hipStream_t st);
+chebdav_status gcn_backward(const Graph *g, const int dims[4], const float *X0, const float *const W[3],
+                            const float *acts, const float *d_out, float *const dW[3], void *ws, size_t ws_bytes,
+                            hipStream_t st);
+chebdav_status gcn_features(const Graph *g, uint64_t seed, int n_gauss, float *X, int64_t ldx, hipStream_t st);
+size_t loss_ws_bytes(int64_t n, int kx, int ku);
+chebdav_status subspace_loss(const float *X, int64_t ldx, const double *U, int64_t ldu, int64_t n, int kx, int ku,
+                             double *loss_host, float *dX, int64_t lddx, void *ws, size_t ws_bytes, hipStream_t st);
+chebdav_status adam_step(float *w, const float *g, float *m, float *v, int64_t count, double lr, double b1,
+                         double b2, double eps, int step, hipStream_t st);
+size_t rr_ws_bytes(int64_t n, int k);
+chebdav_status rayleigh_ritz(const Graph *g, const float *X, int64_t ldx, int k, uint64_t seed, double *V,
+                             int64_t ldv, double *ritz, void *ws, size_t ws_bytes, hipStream_t st);
+
 }  // namespace chebdav

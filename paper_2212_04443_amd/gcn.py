@@ -1,0 +1,171 @@
+"""Learned warm start for the solver (not part of the paper).
+
+A three-layer graph-convolution network (widths 17 -> 64 -> 64 -> 32, FP32)
+maps 16 Gaussian channels plus sqrt(deg / mean deg) to an n x 32 block.  After
+Rayleigh-Ritz the block, sorted by Rayleigh quotient, is passed to the solver
+as V_init, which Alg. 2 filters progressively (steps 2 and 17).  The random
+start stays the fallback: the solver's answer is accepted only by its residual
+certificate.
+
+Training runs on the GPU through the library's own kernels
+(chebdav_gcn_forward / chebdav_gcn_backward / chebdav_subspace_loss /
+chebdav_adam_step): the targets are the k = 32 eigenvectors the FP64 solver
+computes for seeded SBM graphs with N in [10k, 50k], 8..32 blocks, intra-block
+degree 10..30 and inter-block degree 2..6; the loss is the rotation-invariant
+subspace loss.
+
+    python -m paper_2212_04443_amd.gcn train --graphs 512 --epochs 20 --out <file.npz>
+"""
+
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import chebdav as cd
+
+DIMS = (17, 64, 64, 32)
+N_GAUSS = 16
+WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gcn_weights.npz")
+
+
+def _sizes(dims=DIMS):
+    return [dims[l] * dims[l + 1] for l in range(3)]
+
+
+class Net:
+    """Weights of the three layers in one flat device buffer (views per layer)."""
+
+    def __init__(self, flat: torch.Tensor, dims=DIMS):
+        self.dims = tuple(dims)
+        self.flat = flat
+        off = 0
+        self.W = []
+        for l, sz in enumerate(_sizes(dims)):
+            self.W.append(flat[off:off + sz].view(dims[l], dims[l + 1]))
+            off += sz
+
+    @classmethod
+    def glorot(cls, seed: int, dims=DIMS, device="cuda"):
+        rng = np.random.Generator(np.random.PCG64(seed))
+        parts = []
+        for l in range(3):
+            a = np.sqrt(6.0 / (dims[l] + dims[l + 1]))
+            parts.append(rng.uniform(-a, a, size=dims[l] * dims[l + 1]))
+        flat = torch.from_numpy(np.concatenate(parts).astype(np.float32)).to(device)
+        return cls(flat, dims)
+
+    def save(self, path: str, **meta):
+        np.savez(path, flat=self.flat.cpu().numpy(), dims=np.array(self.dims), **meta)
+
+    @classmethod
+    def load(cls, path: str = WEIGHTS_FILE, device="cuda"):
+        z = np.load(path, allow_pickle=False)
+        return cls(torch.from_numpy(z["flat"]).to(device), tuple(int(x) for x in z["dims"]))
+
+
+def training_graph(index: int, base_seed: int = 424242):
+    """Parameters and edges of training graph `index` (seeded)."""
+    import synth
+    rng = np.random.Generator(np.random.PCG64(base_seed + index))
+    n = int(rng.integers(10_000, 50_001))
+    blocks = int(rng.integers(8, 33))
+    d_in = float(rng.uniform(10, 30))
+    d_out = float(rng.uniform(2, 6))
+    edges, _ = synth.sbm(n, blocks, d_in=d_in, d_out=d_out, uneven=True, seed=base_seed + 100_000 + index)
+    return edges, n, dict(n=n, blocks=blocks, d_in=d_in, d_out=d_out)
+
+
+def build_dataset(n_graphs: int, base_seed: int = 424242, k: int = 32, kb: int = 32, m: int = 15, log=None):
+    data = []
+    for i in range(n_graphs):
+        edges, n, meta = training_graph(i, base_seed)
+        g = cd.build_laplacian(edges, n)
+        r = cd.solve(g, cd.make_params(k_want=k, kb=kb, m=m, tol=1e-8, seed=base_seed + i))
+        X0 = cd.gcn_features(g, seed=base_seed + 7 * i + 1, n_gauss=N_GAUSS)
+        data.append(dict(g=g, X0=X0, U=r.evecs, meta=meta, iterations=r.stats["iterations"]))
+        if log and (i + 1) % 64 == 0:
+            log("  dataset %d/%d" % (i + 1, n_graphs))
+    return data
+
+
+def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net: Net | None = None):
+    """Adam, one graph per step, graphs in a seeded random order each epoch."""
+    net = net or Net.glorot(seed)
+    dims = net.dims
+    m = torch.zeros_like(net.flat)
+    v = torch.zeros_like(net.flat)
+    grad = torch.zeros_like(net.flat)
+    sizes = _sizes(dims)
+    dW = []
+    off = 0
+    for l, sz in enumerate(sizes):
+        dW.append(grad[off:off + sz].view(dims[l], dims[l + 1]))
+        off += sz
+    rng = np.random.Generator(np.random.PCG64(seed))
+    history = []
+    step = 0
+    ws_cache = {}
+    for ep in range(epochs):
+        order = rng.permutation(len(data))
+        losses = []
+        lr_ep = lr * (0.5 ** (ep // max(1, epochs // 3)))
+        for i in order:
+            d = data[i]
+            g = d["g"]
+            ws = ws_cache.get(g.n)
+            if ws is None:
+                ws = ws_cache[g.n] = cd.gcn_workspace(g, dims)
+            out, acts = cd.gcn_forward(g, dims, d["X0"], net.W, workspace=ws)
+            loss, dX = cd.subspace_loss(out, d["U"], grad=True)
+            cd.gcn_backward(g, dims, d["X0"], net.W, acts, dX, dW=dW, workspace=ws)
+            step += 1
+            cd.adam_step(net.flat, grad, m, v, lr_ep, step=step)
+            losses.append(loss)
+        history.append(float(np.mean(losses)))
+        if log:
+            log("  epoch %d: mean loss %.4f (lr %.2e)" % (ep, history[-1], lr_ep))
+    return net, history
+
+
+def warm_start(g, net: Net, seed: int = 0, k_total: int | None = None):
+    """V_init for chebdav_solve: Ritz vectors of the network's output block,
+    ascending by Rayleigh quotient.  Returns (V_init, ritz)."""
+    X0 = cd.gcn_features(g, seed=seed, n_gauss=N_GAUSS)
+    out, _ = cd.gcn_forward(g, net.dims, X0, net.W)
+    return cd.rayleigh_ritz(g, out, seed=seed)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
+    ap.add_argument("cmd", choices=["train"])
+    ap.add_argument("--graphs", type=int, default=512)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--seed", type=int, default=5)
+    ap.add_argument("--out", default=WEIGHTS_FILE)
+    a = ap.parse_args(argv)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    data = build_dataset(a.graphs, log=log)
+    t1 = time.time()
+    log("dataset of %d graphs (targets from the FP64 solver) in %.1f s" % (len(data), t1 - t0))
+    net, hist = train(data, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log)
+    torch.cuda.synchronize()
+    t2 = time.time()
+    log("trained %d epochs in %.1f s" % (a.epochs, t2 - t1))
+    net.save(a.out, history=np.array(hist), graphs=a.graphs, epochs=a.epochs, lr=a.lr,
+             train_seconds=t2 - t1, dataset_seconds=t1 - t0)
+    log("saved %s" % a.out)
+
+
+if __name__ == "__main__":
+    main()

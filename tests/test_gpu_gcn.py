@@ -1,0 +1,153 @@
+"""GPU: the learned warm start.  Network forward/backward and the subspace loss
+(FP32 on the GPU) against the FP64 NumPy oracle (itself pinned by finite
+differences), the feature generator, Adam, Rayleigh-Ritz of a block, a short
+training run, and the solver started from the trained network.
+
+Tolerances: forward 1e-5 and gradients 1e-4 relative to the largest entry
+(FP32 arithmetic with sums over at most a few hundred terms per entry; the
+gradient sums over nodes are split and added in FP64)."""
+
+import os
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(got, want):
+    return float(np.abs(got - want).max() / max(np.abs(want).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def setup(cd, oracle_mod, dev):
+    import torch
+    from oracle import gcn as ogcn
+    n = 3000
+    e, _ = synth.sbm(n, 6, d_in=12, d_out=3, uneven=True, seed=21)
+    g = cd.build_laplacian(e, n)
+    o = oracle_mod.build_csr(e, n)
+    dims = (17, 64, 64, 32)
+    W64 = ogcn.glorot(3, dims)
+    W32 = [w.astype(np.float32) for w in W64]
+    X0 = np.random.default_rng(4).standard_normal((n, 17)).astype(np.float32)
+    Wt = [torch.from_numpy(w).cuda() for w in W32]
+    X0t = torch.from_numpy(X0).cuda()
+    return dict(g=g, o=o, dims=dims, W32=W32, Wt=Wt, X0=X0, X0t=X0t, ogcn=ogcn, n=n)
+
+
+def test_forward_matches_oracle(cd, setup):
+    s = setup
+    out, acts = cd.gcn_forward(s["g"], s["dims"], s["X0t"], s["Wt"])
+    want, wacts = s["ogcn"].forward(s["o"], s["X0"].astype(np.float64), [w.astype(np.float64) for w in s["W32"]])
+    assert _rel(out.cpu().numpy(), want) <= 1e-5
+    a = acts.cpu().numpy()
+    n, d1 = s["n"], s["dims"][1]
+    assert _rel(a[: n * d1].reshape(n, d1), wacts[0]) <= 1e-5
+
+
+def test_backward_matches_oracle(cd, setup):
+    import torch
+    s = setup
+    out, acts = cd.gcn_forward(s["g"], s["dims"], s["X0t"], s["Wt"])
+    d_out = np.random.default_rng(9).standard_normal(out.shape).astype(np.float32)
+    dW = cd.gcn_backward(s["g"], s["dims"], s["X0t"], s["Wt"], acts, torch.from_numpy(d_out).cuda())
+    W64 = [w.astype(np.float64) for w in s["W32"]]
+    _, wacts = s["ogcn"].forward(s["o"], s["X0"].astype(np.float64), W64)
+    want = s["ogcn"].backward(s["o"], s["X0"].astype(np.float64), W64, wacts, d_out.astype(np.float64))
+    for l in range(3):
+        err = _rel(dW[l].cpu().numpy(), want[l])
+        print("layer %d gradient rel err %.2e" % (l, err))
+        assert err <= 1e-4
+
+
+def test_loss_and_gradient_match_oracle(cd, oracle_mod, setup):
+    import torch
+    s = setup
+    out, _ = cd.gcn_forward(s["g"], s["dims"], s["X0t"], s["Wt"])
+    lam, Q = np.linalg.eigh(oracle_mod.dense_laplacian(s["o"]))
+    U = np.ascontiguousarray(Q[:, :32])
+    loss, dX = cd.subspace_loss(out, torch.from_numpy(U).cuda())
+    wl, wdX = s["ogcn"].subspace_loss(out.cpu().numpy().astype(np.float64), U)
+    assert abs(loss - wl) <= 1e-10
+    assert _rel(dX.cpu().numpy(), wdX) <= 1e-6
+
+
+def test_features(cd, setup):
+    s = setup
+    X1 = cd.gcn_features(s["g"], seed=5).cpu().numpy()
+    X2 = cd.gcn_features(s["g"], seed=5).cpu().numpy()
+    assert np.array_equal(X1, X2)
+    gauss = X1[:, :16].astype(np.float64)
+    assert abs(gauss.mean()) < 0.02 and abs(gauss.std() - 1.0) < 0.02
+    deg = s["o"].deg.astype(np.float64)
+    assert np.abs(X1[:, 16] - np.sqrt(deg / deg.mean()).astype(np.float32)).max() <= 1e-6
+
+
+def test_adam_step(cd, dev):
+    import torch
+    rng = np.random.default_rng(1)
+    w = rng.standard_normal(1000).astype(np.float32)
+    gr = rng.standard_normal(1000).astype(np.float32)
+    m = rng.standard_normal(1000).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(1000)).astype(np.float32) * 0.01
+    tw, tg, tm, tv = (torch.from_numpy(x.copy()).cuda() for x in (w, gr, m, v))
+    cd.adam_step(tw, tg, tm, tv, 1e-2, 0.9, 0.999, 1e-8, step=3)
+    m2 = 0.9 * m + 0.1 * gr
+    v2 = 0.999 * v + 0.001 * gr * gr
+    w2 = w - 1e-2 * (m2 / (1 - 0.9 ** 3)) / (np.sqrt(v2 / (1 - 0.999 ** 3)) + 1e-8)
+    assert np.abs(tw.cpu().numpy() - w2).max() <= 1e-6
+
+
+def test_rayleigh_ritz_block(cd, oracle_mod, setup):
+    import torch
+    s = setup
+    X = torch.randn(s["n"], 32, dtype=torch.float32, device="cuda")
+    V, ritz = cd.rayleigh_ritz(s["g"], X, seed=1)
+    V, ritz = V.cpu().numpy(), ritz.cpu().numpy()
+    A = oracle_mod.dense_laplacian(s["o"])
+    assert np.linalg.norm(V.T @ V - np.eye(32), 2) <= 1e-12
+    assert (np.diff(ritz) >= 0).all()
+    assert np.abs(V.T @ A @ V - np.diag(ritz)).max() <= 1e-12
+    # V spans the same space as X
+    Xn = X.cpu().numpy().astype(np.float64)
+    Q, _ = np.linalg.qr(Xn)
+    assert np.linalg.norm(V - Q @ (Q.T @ V), 2) <= 1e-6
+
+
+def test_short_training_reduces_loss(cd, dev):
+    from paper_2212_04443_amd import gcn
+    data = gcn.build_dataset(4, base_seed=777)
+    net, hist = gcn.train(data, epochs=12, lr=5e-3, seed=2)
+    print("training loss history", ["%.4f" % h for h in hist])
+    assert hist[-1] < hist[0]
+
+
+def test_trained_warm_start(cd, oracle_mod, dev):
+    """The committed network, trained on the GPU (python -m
+    paper_2212_04443_amd.gcn train), seeds the solver on a held-out SBM graph.
+    The warm-started solve must reach the same eigenpairs (|d lambda| <= 1e-10,
+    fresh residuals <= 1e-8); the iterations and sparse products it saves over
+    the random start are reported (the gain is a measurement, not a pin)."""
+    from paper_2212_04443_amd import gcn
+    if not os.path.exists(gcn.WEIGHTS_FILE):
+        pytest.skip("no trained weights committed yet")
+    net = gcn.Net.load()
+    e, _ = synth.sbm(100_000, 32, d_in=20, d_out=4, uneven=True, seed=987654)
+    n = 100_000
+    g = cd.build_laplacian(e, n)
+    p = cd.make_params(k_want=32, kb=32, m=15, seed=3)
+    rnd = cd.solve(g, p)
+    V0, ritz = gcn.warm_start(g, net, seed=11)
+    warm = cd.solve(g, p, V_init=V0.contiguous())
+    o = oracle_mod.build_csr(e, n)
+    V = warm.evecs.cpu().numpy()
+    ev = warm.evals.cpu().numpy()
+    R = oracle_mod.apply_laplacian(o, np.asfortranarray(V)) - V * ev
+    print("random start: %d iterations, %d filter SpMMs; warm start: %d iterations, %d filter SpMMs"
+          % (rnd.stats["iterations"], rnd.stats["n_spmm_filter"], warm.stats["iterations"],
+             warm.stats["n_spmm_filter"]))
+    assert np.sqrt((R * R).sum(0)).max() <= 1e-8
+    assert np.abs(ev - rnd.evals.cpu().numpy()).max() <= 1e-10

@@ -191,3 +191,30 @@ def test_sbm200k_full_size_parity(cd, oracle_mod, dev, form):
     assert np.linalg.norm(V.T @ V - np.eye(32), 2) <= 1e-12
     if form == "f64":
         assert abs(st["iterations"] - ref.iterations) <= 2
+
+
+def test_streaming_warm_start(cd, oracle_mod, dev):
+    """Warm start from the eigenvectors of a slightly different graph (the
+    streaming-graph use of V_init): after 0.5% of the edges are rewired, the
+    previous eigenvectors, passed as V_init, are filtered progressively and
+    reach the new eigenpairs with fewer iterations than a random start."""
+    import torch
+    e, n, cfg = synth.make_config_graph("sbm200k")
+    g0 = cd.build_laplacian(e, n)
+    p = cd.make_params(k_want=32, kb=32, m=15, seed=1)
+    prev = cd.solve(g0, p)
+    rng = np.random.default_rng(5)
+    keep = rng.random(len(e)) >= 0.005
+    new = rng.integers(0, n, size=(int((~keep).sum()), 2))
+    e2 = np.concatenate([e[keep], new]).astype(np.int64)
+    g1 = cd.build_laplacian(e2, n)
+    rnd = cd.solve(g1, p)
+    warm = cd.solve(g1, p, V_init=prev.evecs.contiguous())
+    o = oracle_mod.build_csr(e2, n)
+    V, ev = warm.evecs.cpu().numpy(), warm.evals.cpu().numpy()
+    R = oracle_mod.apply_laplacian(o, np.asfortranarray(V)) - V * ev
+    print("streaming: random start %d iterations, previous-eigenvector start %d iterations"
+          % (rnd.stats["iterations"], warm.stats["iterations"]))
+    assert np.sqrt((R * R).sum(0)).max() <= 1e-8
+    assert np.abs(ev - rnd.evals.cpu().numpy()).max() <= 1e-10
+    assert warm.stats["iterations"] < rnd.stats["iterations"]
