@@ -277,6 +277,24 @@ __global__ void k_compact(const int64_t *__restrict__ off, const int32_t *__rest
     }
 }
 
+// Row boundaries that split the cost row_ptr[r] + 4 r into eight equal parts
+// (binary search over the monotone cost).
+__global__ void k_xcd_split(const int64_t *__restrict__ row_ptr, int64_t n, int64_t *__restrict__ out) {
+    const int x = threadIdx.x;
+    if (x > 8) return;
+    const int64_t total = row_ptr[n] + 4 * n;
+    const int64_t target = total / 8 * x + (total % 8) * x / 8;
+    int64_t lo = 0, hi = n;  // first r with cost(r) >= target
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (row_ptr[mid] + 4 * mid < target)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    out[x] = x == 8 ? n : lo;
+}
+
 chebdav_status scan_counts(const int32_t *in, int64_t n, int64_t *out, int64_t *bsum,
                            hipStream_t st) {
     const int64_t nb = ceil_div(n, kScanTile);
@@ -447,6 +465,25 @@ chebdav_status build_graph(const int64_t *edges, int64_t E, int64_t n, int on_de
     }
     g->n_isolated = hstats[0];
     g->max_deg = hstats[1];
+    // per-XCD row ranges for the sparse step (bsum has room: nb >= 1 entries, use counters' buffer)
+    {
+        int64_t *d_split = static_cast<int64_t *>(lists.p);  // 2n >= 9 entries unless n < 5
+        DevBuf small;
+        if (2 * n < 9) {
+            if (dev_alloc<int64_t>(small, 9) != CHEBDAV_OK) {
+                cleanup();
+                return fail(CHEBDAV_ENOMEM, "allocation failed");
+            }
+            d_split = static_cast<int64_t *>(small.p);
+        }
+        hipLaunchKernelGGL(k_xcd_split, dim3(1), dim3(64), 0, st, g->row_ptr, n, d_split);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(g->xcd_row, d_split, sizeof(g->xcd_row), hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            cleanup();
+            return fail(CHEBDAV_EHIP, "XCD split failed");
+        }
+    }
     *out = g;
     return CHEBDAV_OK;
 }

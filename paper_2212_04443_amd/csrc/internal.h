@@ -50,6 +50,14 @@ struct Graph {
     int32_t *deg = nullptr;      // [n]
     double *dinv = nullptr;      // [n]
     float *dinv32 = nullptr;     // [n], dinv rounded to FP32 (for the FP32 filter)
+    // Row ranges of the sparse step per XCD: XCD x owns rows [xcd_row[x], xcd_row[x+1]),
+    // chosen so that nnz + 4 * rows is about equal across the eight XCDs.
+    int64_t xcd_row[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// Kernel-argument copy of Graph::xcd_row.
+struct XcdRanges {
+    int64_t b[9];
 };
 
 // Simple bump allocator over a caller-provided workspace.

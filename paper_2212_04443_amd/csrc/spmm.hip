@@ -10,9 +10,10 @@
 // gathers 64/G neighbour rows with one load instruction per lane.  The group
 // loads up to G column indices and their dinv values cooperatively (coalesced)
 // and broadcasts them lane to lane; neighbour sums run in ascending column
-// order, so results are deterministic.  Blocks are renumbered so that each of
-// the eight XCDs walks a contiguous range of rows (the gathered rows of
-// block-structured graphs then stay in that XCD's L2).
+// order, so results are deterministic.  Each of the eight XCDs walks its own
+// contiguous range of rows (the gathered rows of block-structured graphs then
+// stay in that XCD's L2); the ranges are balanced by nonzeros, so graphs whose
+// degrees vary along the node order (power laws, hubs first) keep every XCD busy.
 #include <algorithm>
 
 #include "device_util.h"
@@ -67,18 +68,17 @@ __global__ void __launch_bounds__(kBlock)
     k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                 const T *__restrict__ dinv, T alpha, T beta, T gamma, const T *__restrict__ U,
                 int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
-                int w) {
+                int w, XcdRanges xr) {
     constexpr int GPB = kBlock / G;  // rows per block
     constexpr int CH = Chunk<G>::CH, PER = Chunk<G>::PER, UNR = Chunk<G>::UNR;
     const int lane = lane_id();
     const int gl = lane & (G - 1);
-    // XCD-aware renumbering: gridDim.x is a multiple of 8; consecutive hardware
-    // block ids alternate XCDs, so block b works on logical block
-    // (b mod 8) * (grid / 8) + b / 8.
-    const int64_t per = gridDim.x / kXcds;
-    const int64_t blk = (int64_t)(blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
-    const int64_t r = blk * GPB + threadIdx.x / G;
-    if (r >= n) return;  // uniform within a group
+    // XCD-aware mapping: consecutive hardware block ids alternate over the eight
+    // XCDs, so block b runs on XCD b mod 8; that XCD walks its own contiguous row
+    // range (balanced by nonzeros at graph build) in order, block b / 8 next.
+    const int xcd = blockIdx.x % kXcds;
+    const int64_t r = xr.b[xcd] + (int64_t)(blockIdx.x / kXcds) * GPB + threadIdx.x / G;
+    if (r >= xr.b[xcd + 1]) return;  // uniform within a group
     const int c0 = gl * VE;
     const bool active = c0 < w;
     const int64_t beg = row_ptr[r], end = row_ptr[r + 1];
@@ -157,14 +157,17 @@ chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *
     int G = 1;
     while (G < lanes) G <<= 1;
     const int64_t rows_per_block = kBlock / G;
-    int64_t grid = ceil_div(g->n, rows_per_block);
-    grid = ceil_div(grid, kXcds) * kXcds;
+    XcdRanges xr;
+    int64_t most = 0;
+    for (int x = 0; x <= kXcds; ++x) xr.b[x] = g->xcd_row[x];
+    for (int x = 0; x < kXcds; ++x) most = std::max<int64_t>(most, xr.b[x + 1] - xr.b[x]);
+    const int64_t grid = std::max<int64_t>(1, ceil_div(most, rows_per_block)) * kXcds;
     if (grid > INT32_MAX) return fail(CHEBDAV_EUNSUPPORTED, "grid too large");
     const dim3 gr((unsigned)grid), bl(kBlock);
 #define CD_CASE(GG)                                                                                 \
     case GG:                                                                                        \
         hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG>), gr, bl, 0, st, g->n, g->row_ptr, g->col,   \
-                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w);                               \
+                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr);                           \
         break;
     switch (G) {
         CD_CASE(1)

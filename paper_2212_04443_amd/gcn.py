@@ -133,7 +133,7 @@ def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net
     return net, history
 
 
-def warm_start(g, net: Net, seed: int = 0, k_total: int | None = None):
+def warm_start(g, net: Net, seed: int = 0):
     """V_init for chebdav_solve: Ritz vectors of the network's output block,
     ascending by Rayleigh quotient.  Returns (V_init, ritz)."""
     X0 = cd.gcn_features(g, seed=seed, n_gauss=N_GAUSS)
@@ -141,9 +141,37 @@ def warm_start(g, net: Net, seed: int = 0, k_total: int | None = None):
     return cd.rayleigh_ritz(g, out, seed=seed)
 
 
+def evaluate(g, net: Net, k: int, kb: int, m: int, seeds, filter_dtype=cd.F64):
+    """Random start vs warm start from the network, same solver settings, for each
+    seed (the seed drives the random vectors and the network's input channels).
+    Returns a list of dicts with iterations, filter sparse products and seconds
+    (the warm-start time includes feature generation, inference and Rayleigh-Ritz)."""
+    rows = []
+    for sd in seeds:
+        p = cd.make_params(k_want=k, kb=kb, m=m, tol=1e-8, seed=sd, filter_dtype=filter_dtype)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = cd.solve(g, p)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        V0, _ = warm_start(g, net, seed=sd)
+        w = cd.solve(g, p, V_init=V0.contiguous())
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        rows.append(dict(seed=sd, random_iterations=r.stats["iterations"], warm_iterations=w.stats["iterations"],
+                         random_spmm=r.stats["n_spmm_filter"] + r.stats["n_spmm_other"],
+                         warm_spmm=w.stats["n_spmm_filter"] + w.stats["n_spmm_other"],
+                         random_s=t1 - t0, warm_s=t2 - t1,
+                         max_dlambda=float((r.evals - w.evals).abs().max().item()),
+                         warm_max_residual=w.stats["max_residual"]))
+    return rows
+
+
 def main(argv=None):
-    ap = argparse.ArgumentParser(description="train the warm-start network on the GPU")
-    ap.add_argument("cmd", choices=["train"])
+    ap = argparse.ArgumentParser(description="train or evaluate the warm-start network on the GPU")
+    ap.add_argument("cmd", choices=["train", "evaluate"])
+    ap.add_argument("--workload", default="sbm1m")
+    ap.add_argument("--seeds", type=int, default=8)
     ap.add_argument("--graphs", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=3e-3)
@@ -153,6 +181,24 @@ def main(argv=None):
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
+
+    if a.cmd == "evaluate":
+        import json
+        import synth
+        edges, n, cfg = synth.make_config_graph(a.workload)
+        g = cd.build_laplacian(edges, n)
+        net = Net.load()
+        rows = evaluate(g, net, cfg["k"], cfg["kb"], cfg["m"], seeds=range(1, a.seeds + 1))
+        for r in rows:
+            log(json.dumps(r))
+        summ = dict(workload=a.workload, seeds=a.seeds,
+                    random_iterations=float(np.mean([r["random_iterations"] for r in rows])),
+                    warm_iterations=float(np.mean([r["warm_iterations"] for r in rows])),
+                    random_ms=1e3 * float(np.median([r["random_s"] for r in rows])),
+                    warm_ms=1e3 * float(np.median([r["warm_s"] for r in rows])),
+                    max_dlambda=max(r["max_dlambda"] for r in rows))
+        print(json.dumps(summ), flush=True)
+        return
 
     t0 = time.time()
     data = build_dataset(a.graphs, log=log)
