@@ -263,6 +263,37 @@ chebdav_status chebdav_small_eig_workspace_size(int n, size_t *bytes);
 chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *evals, double *evecs,
                                  int64_t ldy, void *workspace, size_t ws_bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Clustering tail of spectral clustering (Alg. 1, steps 3-4).
+ *
+ * Row normalization of the eigenvector block, then Lloyd's K-means:
+ *   F(i, :) = U(i, :) / ||U(i, :)||_2 (a zero row stays zero);
+ *   K initial centres by farthest-first traversal: the first is row
+ *   floor(u n), u = ((w1 << 32 | w0) >> 11) / 2^53 from Philox4x32-10 with
+ *   counter (0, 0, 0, 1) and key (seed mod 2^32, seed >> 32), computed in
+ *   integer arithmetic; each next one is the row with the largest squared
+ *   distance to its nearest chosen centre (lowest row index among ties);
+ *   each round labels every row with its nearest centre (lowest centre index
+ *   among ties) and moves every centre to the mean of its rows (a centre with no
+ *   rows stays); rounds stop when no label changes or after max_iter rounds.
+ *   Squared distances are sums over the coordinates in ascending order with
+ *   separately rounded subtract, multiply and add.  All sums over rows use
+ *   fixed row ranges and a fixed order (deterministic results).
+ *
+ * U: device double, n x k, row-major, leading dimension ldu >= k; 1 <= k <= 64.
+ * labels: device int32[n] (output).  centres: device double, n_clusters x k,
+ * row-major, leading dimension k (output).  rounds (host, nullable): Lloyd
+ * rounds run.  inertia (host, nullable): sum over rows of the squared distance
+ * to the assigned centre.  1 <= n_clusters <= min(n, 256) and n_clusters * k
+ * <= 8000.  Workspace from chebdav_cluster_workspace_size.  Synchronizes the
+ * stream once per round.  Errors: EINVAL (sizes, NULL buffers, max_iter < 1),
+ * ENOMEM (workspace too small), EUNSUPPORTED (n_clusters * k too large).
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_cluster_workspace_size(int64_t n, int k, int n_clusters, size_t *bytes);
+chebdav_status chebdav_cluster(const double *U, int64_t ldu, int64_t n, int k, int n_clusters, int max_iter,
+                               uint64_t seed, int32_t *labels, double *centres, int *rounds, double *inertia,
+                               void *workspace, size_t ws_bytes, void *hip_stream);
+
 /* Fills X(:, j), j < w (device double, n x w, row-major, ld), with Philox4x32-10
  * uniforms on [-1, 1): entry (r, j) uses counter (r mod 2^32, r >> 32,
  * first_col + j, 0) and key (seed mod 2^32, seed >> 32); value =

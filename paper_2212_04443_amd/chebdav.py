@@ -35,6 +35,7 @@ EXPORTED = [
     "chebdav_gcn_workspace_size", "chebdav_gcn_forward", "chebdav_gcn_backward", "chebdav_gcn_features",
     "chebdav_subspace_loss_workspace_size", "chebdav_subspace_loss", "chebdav_adam_step",
     "chebdav_rayleigh_ritz_workspace_size", "chebdav_rayleigh_ritz",
+    "chebdav_cluster_workspace_size", "chebdav_cluster",
 ]
 
 
@@ -98,6 +99,8 @@ def _load():
         "chebdav_adam_step": [p, p, p, p, i64, d, d, d, d, i32, p],
         "chebdav_rayleigh_ritz_workspace_size": [p, i32, P(sz)],
         "chebdav_rayleigh_ritz": [p, p, i64, i32, u64, p, i64, p, p, sz, p],
+        "chebdav_cluster_workspace_size": [i64, i32, i32, P(sz)],
+        "chebdav_cluster": [p, i64, i64, i32, i32, i32, u64, p, p, P(i32), P(d), p, sz, p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -391,3 +394,21 @@ def rayleigh_ritz(g: Graph, X: torch.Tensor, seed: int = 0, stream=None):
     _check(_lib.chebdav_rayleigh_ritz(g.handle, _ptr(X), _ld(X), k, seed, _ptr(V), _ld(V), _ptr(ritz), _ptr(ws),
                                       ws.numel(), _stream(stream)))
     return V, ritz
+
+
+def cluster(U: torch.Tensor, n_clusters: int, seed: int = 0, max_iter: int = 100, stream=None):
+    """chebdav_cluster: row normalization of the eigenvector block U (float64,
+    n x k) and K-means.  Returns (labels int32[n], centres n_clusters x k, rounds,
+    inertia)."""
+    n, k = U.shape
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_cluster_workspace_size(n, k, n_clusters, ctypes.byref(nb)))
+    ws = _workspace(nb.value, U.device)
+    labels = torch.empty(n, dtype=torch.int32, device=U.device)
+    C = torch.empty(n_clusters, k, dtype=torch.float64, device=U.device)
+    rounds = ctypes.c_int()
+    inertia = ctypes.c_double()
+    _check(_lib.chebdav_cluster(_ptr(U), _ld(U), n, k, n_clusters, max_iter, seed, _ptr(labels), _ptr(C),
+                                ctypes.byref(rounds), ctypes.byref(inertia), _ptr(ws), ws.numel(),
+                                _stream(stream)))
+    return labels, C, rounds.value, inertia.value

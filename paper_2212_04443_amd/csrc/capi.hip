@@ -201,6 +201,18 @@ chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *ev
     return small_eig(H, ldh, n, evals, evecs, ldy, workspace, ws_bytes, as_stream(hip_stream));
 }
 
+chebdav_status chebdav_cluster_workspace_size(int64_t n, int k, int n_clusters, size_t *bytes) {
+    if (!bytes) return fail(CHEBDAV_EINVAL, "bytes is NULL");
+    return cluster_ws_bytes(n, k, n_clusters, bytes);
+}
+
+chebdav_status chebdav_cluster(const double *U, int64_t ldu, int64_t n, int k, int n_clusters, int max_iter,
+                               uint64_t seed, int32_t *labels, double *centres, int *rounds, double *inertia,
+                               void *workspace, size_t ws_bytes, void *hip_stream) {
+    return cluster(U, ldu, n, k, n_clusters, max_iter, seed, labels, centres, rounds, inertia, workspace, ws_bytes,
+                   as_stream(hip_stream));
+}
+
 chebdav_status chebdav_philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
                                    uint64_t first_col, void *hip_stream) {
     if (!X || n < 0 || w < 0 || ld < w) return fail(CHEBDAV_EINVAL, "bad arguments");

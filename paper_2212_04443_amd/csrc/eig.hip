@@ -152,6 +152,129 @@ __global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, i
     tridiag_run(Ag, H, ldh, n, Vh, d, e, tau, v, wsh, red);
 }
 
+// Register-resident variant for n <= 16 T: the working matrix is spread over a
+// 16 x 16 thread grid, thread (pr, pc) holding A(pr + 16 a, pc + 16 b) for a, b < T,
+// so the product A v and the rank-2 update touch no shared memory; only the
+// vectors (column k, v, p, w) go through LDS, and the sums over the column index
+// are lane shuffles inside 16-lane groups.  Tiles whose rows (or columns) all lie
+// in the finished leading part are skipped (uniform branches).
+template <int T>
+__global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ H, int64_t ldh, int n,
+                                                     double *__restrict__ Vh, double *__restrict__ d,
+                                                     double *__restrict__ e, double *__restrict__ tau) {
+    constexpr int P = 16, NV = P * T;
+    __shared__ double xs[NV], vs[NV], ws[NV], scal[2];
+    const int tid = threadIdx.x, pr = tid / P, pc = tid % P;
+    double A[T][T];
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int i = pr + P * a, j = pc + P * b;
+            A[a][b] = (i < n && j < n) ? H[(int64_t)i * ldh + j] : 0.0;
+        }
+    for (int k = 0; k + 2 < n; ++k) {
+        const int m = n - k - 1;
+        // column k (rows k..n-1) into xs
+        if (pc == k % P) {
+            const int bk = k / P;
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                const int i = pr + P * a;
+                double val = 0.0;
+#pragma unroll
+                for (int b = 0; b < T; ++b) val = (b == bk) ? A[a][b] : val;
+                if (i >= k && i < n) xs[i] = val;
+            }
+        }
+        __syncthreads();
+        // reflector (wavefront 0): v = x - alpha e1 in vs (zero outside rows k+1..n-1)
+        if (tid < kWave) {
+            double part = 0.0;
+            for (int i = k + 2 + tid; i < n; i += kWave) part += xs[i] * xs[i];
+            const double ss = wave_sum(part);
+            const double x0 = xs[k + 1];
+            double t = 0.0, v0 = 0.0, alpha = x0;
+            if (ss != 0.0) {
+                alpha = -copysign(sqrt(x0 * x0 + ss), x0);
+                v0 = x0 - alpha;
+                t = 2.0 / (v0 * v0 + ss);
+            }
+            for (int i = tid; i < NV; i += kWave) {
+                double v = 0.0;
+                if (t != 0.0 && i > k && i < n) v = (i == k + 1) ? v0 : xs[i];
+                vs[i] = v;
+                if (i > k && i < n) Vh[(int64_t)k * n + (i - k - 1)] = v;
+            }
+            if (tid == 0) {
+                scal[0] = t;
+                tau[k] = t;
+                e[k] = alpha;
+                d[k] = xs[k];
+            }
+        }
+        __syncthreads();
+        const double t = scal[0];
+        if (t != 0.0) {
+            // p = t A v: partial sums over this thread's columns, then over the 16 lanes of the row group
+            double vc[T];
+#pragma unroll
+            for (int b = 0; b < T; ++b) vc[b] = vs[pc + P * b];
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                if (P * (a + 1) - 1 <= k) continue;  // rows of this tile are all finished
+                double sacc = 0.0;
+#pragma unroll
+                for (int b = 0; b < T; ++b)
+                    if (P * (b + 1) - 1 > k) sacc += A[a][b] * vc[b];
+#pragma unroll
+                for (int o = P / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, P);
+                if (pc == 0) xs[pr + P * a] = t * sacc;
+            }
+            __syncthreads();
+            // w = p - (t/2)(p^T v) v (wavefront 0)
+            if (tid < kWave) {
+                double part = 0.0;
+                for (int i = k + 1 + tid; i < n; i += kWave) part += xs[i] * vs[i];
+                const double K = 0.5 * t * wave_sum(part);
+                for (int i = tid; i < NV; i += kWave) ws[i] = (i > k && i < n) ? xs[i] - K * vs[i] : 0.0;
+            }
+            __syncthreads();
+            // A <- A - v w^T - w v^T
+            double wc[T];
+#pragma unroll
+            for (int b = 0; b < T; ++b) wc[b] = ws[pc + P * b];
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                if (P * (a + 1) - 1 <= k) continue;
+                const double vr = vs[pr + P * a], wr = ws[pr + P * a];
+#pragma unroll
+                for (int b = 0; b < T; ++b)
+                    if (P * (b + 1) - 1 > k) A[a][b] -= vr * wc[b] + wr * vc[b];
+            }
+        }
+        (void)m;
+    }
+    // trailing 2 x 2 block (or the 1 x 1 matrix)
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int i = pr + P * a, j = pc + P * b;
+            if (n >= 2) {
+                if (i == n - 2 && j == n - 2) d[n - 2] = A[a][b];
+                if (i == n - 1 && j == n - 2) e[n - 2] = A[a][b];
+                if (i == n - 1 && j == n - 1) {
+                    d[n - 1] = A[a][b];
+                    e[n - 1] = 0.0;
+                }
+            } else if (i == 0 && j == 0) {
+                d[0] = A[a][b];
+                e[0] = 0.0;
+            }
+        }
+}
+
 // Number of eigenvalues of T smaller than x (Sturm sequence).
 __device__ inline int sturm(const double *d, const double *e, int n, double x, double pivmin) {
     int c = 0;
@@ -432,7 +555,21 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
     EigWs s = eig_layout(a, n);
-    if (n <= kLdsMaxN)
+    if (n <= 160) {
+        const int T = 2 * (int)ceil_div(n, 32);
+#define CD_TRI(TT)                                                                                   \
+    case TT:                                                                                         \
+        hipLaunchKernelGGL(k_tridiag_reg<TT>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); \
+        break;
+        switch (T) {
+            CD_TRI(2)
+            CD_TRI(4)
+            CD_TRI(6)
+            CD_TRI(8)
+            CD_TRI(10)
+        }
+#undef CD_TRI
+    } else if (n <= kLdsMaxN)
         hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(512), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
     else
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(512), 0, st, H, ldh, n, s.A, s.Vh, s.d, s.e, s.tau);

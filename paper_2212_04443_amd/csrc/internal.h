@@ -154,6 +154,12 @@ chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *R
 chebdav_status h_insert(double *H, int64_t ldh, const double *C, int k, int kb, hipStream_t st);
 // H(0:k, 0:k) = diag(d).
 chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStream_t st);
+// Deferred rotation (active block = B Q): H columns from Cf = [B, X]^T A X, and
+// Q <- [[Q, 0], [0, I]] Y.
+chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
+                         hipStream_t st);
+chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
+                            int nc, double *Qn, int64_t ldn, hipStream_t st);
 
 // ---- eig.hip
 size_t eig_ws_bytes(int n);
@@ -179,6 +185,10 @@ chebdav_status subspace_loss(const float *X, int64_t ldx, const double *U, int64
                              double *loss_host, float *dX, int64_t lddx, void *ws, size_t ws_bytes, hipStream_t st);
 chebdav_status adam_step(float *w, const float *g, float *m, float *v, int64_t count, double lr, double b1,
                          double b2, double eps, int step, hipStream_t st);
+chebdav_status cluster_ws_bytes(int64_t n, int k, int K, size_t *bytes);
+chebdav_status cluster(const double *U, int64_t ldu, int64_t n, int k, int K, int max_iter, uint64_t seed,
+                       int32_t *labels, double *centres, int *rounds, double *inertia, void *ws, size_t ws_bytes,
+                       hipStream_t st);
 size_t rr_ws_bytes(int64_t n, int k);
 chebdav_status rayleigh_ritz(const Graph *g, const float *X, int64_t ldx, int k, uint64_t seed, double *V,
                              int64_t ldv, double *ritz, void *ws, size_t ws_bytes, hipStream_t st);

@@ -118,6 +118,43 @@ __global__ void k_h_set_diag(double *__restrict__ H, int64_t ldh, const double *
     H[(int64_t)i * ldh + j] = (i == j) ? dg[i] : 0.0;
 }
 
+// Deferred rotation of the search basis.  The active block is kept as B Q:
+// B (n x kr, orthonormal, in HBM) and a small kr x ka matrix Q.
+// C(i, j) = sum_{r < kr} Q(r, i) Cf(r, j) for i < ka, and Cf(kr + i - ka, j) for
+// ka <= i < ka + kb: the new columns of H = [B Q, X]^T (A X) from Cf = [B, X]^T (A X).
+__global__ void k_proj_cols(const double *__restrict__ Q, int64_t ldq, const double *__restrict__ Cf,
+                            int kr, int ka, int kb, double *__restrict__ C) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (ka + kb) * kb) return;
+    const int i = e / kb, j = e % kb;
+    double t;
+    if (i < ka) {
+        t = 0.0;
+        for (int r = 0; r < kr; ++r) t += Q[(int64_t)r * ldq + i] * Cf[(int64_t)r * kb + j];
+    } else {
+        t = Cf[(int64_t)(kr + i - ka) * kb + j];
+    }
+    C[e] = t;
+}
+
+// Qn = [[Q, 0], [0, I_kb]] Y(:, 1:nc): rows r < kr take sum_{i < ka} Q(r, i) Y(i, j);
+// rows kr + t take Y(ka + t, j).
+__global__ void k_extend_basis(const double *__restrict__ Q, int64_t ldq, const double *__restrict__ Y,
+                               int64_t ldy, int kr, int ka, int kb, int nc, double *__restrict__ Qn,
+                               int64_t ldn) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(kr + kb) * nc) return;
+    const int r = (int)(e / nc), j = (int)(e % nc);
+    double t;
+    if (r < kr) {
+        t = 0.0;
+        for (int i = 0; i < ka; ++i) t += Q[(int64_t)r * ldq + i] * Y[(int64_t)i * ldy + j];
+    } else {
+        t = Y[(int64_t)(ka + r - kr) * ldy + j];
+    }
+    Qn[(int64_t)r * ldn + j] = t;
+}
+
 }  // namespace
 
 chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *Rinv, int *dep,
@@ -139,6 +176,26 @@ chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStr
     if (k == 0) return CHEBDAV_OK;
     const int64_t total = (int64_t)k * k;
     hipLaunchKernelGGL(k_h_set_diag, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, H, ldh, d, k);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
+                         hipStream_t st) {
+    const int total = (ka + kb) * kb;
+    if (total == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_proj_cols, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, Q, ldq, Cf, kr, ka,
+                       kb, C);
+    CD_LAUNCH_CHECK();
+    return CHEBDAV_OK;
+}
+
+chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
+                            int nc, double *Qn, int64_t ldn, hipStream_t st) {
+    const int64_t total = (int64_t)(kr + kb) * nc;
+    if (total == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_extend_basis, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, Q, ldq, Y, ldy,
+                       kr, ka, kb, nc, Qn, ldn);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }

@@ -79,7 +79,7 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
 }
 
 struct Layout {
-    double *Vl, *Va[2], *W[2], *Vtmp, *H, *C, *Y, *D, *res, *part, *hd, *ev;
+    double *Vl, *Va[2], *W[2], *Vtmp, *H, *C, *C2, *Y, *Q[2], *D, *res, *part, *hd, *ev, *ones;
     int32_t *map;
     void *filt, *orthw, *eigw;
     size_t filt_b, orth_b, eig_b;
@@ -93,7 +93,10 @@ Layout layout(Arena &a, int64_t n, const Resolved &r) {
     L.Vtmp = a.take<double>((size_t)n * r.kb);
     L.H = a.take<double>((size_t)r.act_max * r.act_max);
     L.C = a.take<double>((size_t)r.act_max * r.kb);
+    L.C2 = a.take<double>((size_t)r.act_max * r.kb);
     L.Y = a.take<double>((size_t)r.act_max * r.act_max);
+    for (int i = 0; i < 2; ++i) L.Q[i] = a.take<double>((size_t)r.act_max * r.act_max);
+    L.ones = a.take<double>(r.act_max);
     L.D = a.take<double>(r.act_max);
     L.res = a.take<double>(std::max(r.act_max, r.lmax));
     L.hd = a.take<double>(r.act_max);
@@ -191,7 +194,15 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             S.n_random += kb - take;
         }
     }
-    int ki = kb, kc = 0, ksub = 0, kact = 0, cur = 0;
+    // Basis bookkeeping.  The active block V(:, kc+1 : ksub) of the algorithm is
+    // B Q(:, 1:kact), with B = Va[cur](:, 1:kr) (orthonormal) and the small kr x
+    // kact matrix Q[qc]; W[cur](:, 1:kr) = A B.  The columns of B and of the locked
+    // vectors Vl(:, kcb+1 : kc) = B Q_locked span the same space as [Vl(:, kcb+1 :
+    // kc), B Q], so V(:, 1:ksub) spans [Vl(:, 1:kcb), B], an orthonormal set of
+    // kcb + kr = kc + kact = ksub columns.  The tall products B Q and (A B) Q are
+    // formed only for the kb leading Ritz pairs (residuals, locking, next block)
+    // and, as the rotation of step 11, when a restart drops columns or B is full.
+    int ki = kb, kc = 0, kact = 0, kr = 0, kcb = 0, cur = 0, qc = 0;
     std::vector<double> locked;  // eigenvalues in locking order (column order of Vl)
     bool use_f64_filter = r.fdt == CHEBDAV_F64;
     EventPair evp;
@@ -199,26 +210,46 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         CD_HIP(hipEventCreate(&evp.b));
         CD_HIP(hipEventCreate(&evp.e));
     }
+    CD_TRY(fill_f64(L.ones, am, 1.0, st));
+    const int64_t tblk = (int64_t)(align_up((size_t)n * kb * sizeof(double), 256) / sizeof(double));
+    double *T0 = static_cast<double *>(L.filt), *T1 = T0 + tblk;  // filter scratch, free between filters
+    // rotation: B <- B Q(:, 1:keep), A B <- (A B) Q(:, 1:keep), Q <- I
+    auto compress = [&](int keep) -> chebdav_status {
+        Seg2 vs, wsg;
+        vs.X1 = L.Va[cur];
+        vs.ld1 = am;
+        vs.p1 = kr;
+        wsg.X1 = L.W[cur];
+        wsg.ld1 = am;
+        wsg.p1 = kr;
+        CD_TRY(update(vs, L.Q[qc], am, 1.0, 0.0, L.Va[1 - cur], am, keep, n, st));
+        CD_TRY(update(wsg, L.Q[qc], am, 1.0, 0.0, L.W[1 - cur], am, keep, n, st));
+        cur = 1 - cur;
+        CD_TRY(h_set_diag(L.Q[qc], am, L.ones, keep, st));
+        kr = keep;
+        kcb = kc;
+        return CHEBDAV_OK;
+    };
     chebdav_status result = CHEBDAV_ENOCONV;
     int it = 0;
     std::vector<double> D(am), res(kb);
     while (it < r.itmax) {
         ++it;
-        double *Xnew = L.Va[cur] + kact;
+        double *Xnew = L.Va[cur] + kr;
         // step 5: filter
         const chebdav_dtype fdt = use_f64_filter ? CHEBDAV_F64 : CHEBDAV_F32;
         CD_TRY(run_filter(g, L.Vtmp, kb, Xnew, am, kb, r.m, low_nwb, upperb, lowb, fdt, L.filt, L.filt_b,
                           st, evp.b, evp.e));
         S.n_spmm_filter += r.m;
         if (fdt == CHEBDAV_F32) S.n_spmm_filter_f32 += r.m;
-        // step 6: orthonormalize against V(:, 1:ksub) = [Vl(:, 1:kc), Va(:, 1:kact)]
+        // step 6: orthonormalize against V(:, 1:ksub), spanned by [Vl(:, 1:kcb), B]
         Seg2 V;
         V.X1 = L.Vl;
         V.ld1 = r.lmax;
-        V.p1 = kc;
+        V.p1 = kcb;
         V.X2 = L.Va[cur];
         V.ld2 = am;
-        V.p2 = kact;
+        V.p2 = kr;
         int nrep = 0;
         CD_TRY(orthonormalize(V, Xnew, am, kb, n, r.seed, &next_col, &nrep, L.orthw, L.orth_b, st));
         S.n_replaced += nrep;
@@ -229,45 +260,53 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             S.t_filter_ms += ms;
             S.n_filter_launches += r.m;
         }
-        // step 7: W(:, kact+1 : kact+kb) = A V_new
-        CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, Xnew, am, nullptr, 0, L.W[cur] + kact, am,
+        // step 7: W(:, kr+1 : kr+kb) = A V_new
+        CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, Xnew, am, nullptr, 0, L.W[cur] + kr, am,
                                                  kb, st)));
         S.n_spmm_other += 1;
-        kact += kb;
-        ksub += kb;
-        // step 8: H(1:kact, kact-kb+1:kact) = V(:, kc+1:ksub)^T W(:, kact-kb+1:kact), symmetrized
+        // step 8: H(1:kact+kb, new) = [B Q, V_new]^T A V_new, symmetrized
         {
-            Seg2 va;
-            va.X1 = L.Va[cur];
-            va.ld1 = am;
-            va.p1 = kact;
-            CD_TRY(gram(va, L.W[cur] + kact - kb, am, kb, n, L.C, kb, L.part, st));
-            CD_TRY(h_insert(L.H, am, L.C, kact, kb, st));
+            Seg2 bs;
+            bs.X1 = L.Va[cur];
+            bs.ld1 = am;
+            bs.p1 = kr + kb;
+            CD_TRY(gram(bs, L.W[cur] + kr, am, kb, n, L.C, kb, L.part, st));
+            CD_TRY(proj_cols(L.Q[qc], am, L.C, kr, kact, kb, L.C2, st));
+            CD_TRY(h_insert(L.H, am, L.C2, kact + kb, kb, st));
         }
-        // step 9: H Y = Y D, ascending
-        CD_TRY(small_eig(L.H, am, kact, L.D, L.Y, am, L.eigw, L.eig_b, st));
-        const int kold = kact;
-        // step 10: inner restart
+        // step 9: H Y = Y D, ascending; Q <- [[Q, 0], [0, I]] Y
+        CD_TRY(small_eig(L.H, am, kact + kb, L.D, L.Y, am, L.eigw, L.eig_b, st));
+        CD_TRY(extend_basis(L.Q[qc], am, L.Y, am, kr, kact, kb, kact + kb, L.Q[1 - qc], am, st));
+        qc = 1 - qc;
+        kr += kb;
+        kact += kb;
+        // steps 10-11: inner restart, with the rotation
+        bool rotated = false;
         if (kact + kb > am) {
             kact = r.k_ri;
-            ksub = kc + kact;
+            CD_TRY(compress(kact));
+            rotated = true;
         }
-        // step 11: rotation, out of place
-        {
+        // step 12: residuals of the first kb active pairs, from PV = B Q(:, 1:nres)
+        // and PW = (A B) Q(:, 1:nres) (the rotated blocks themselves after a restart)
+        const int nres = std::min(kb, kact);
+        const double *PV = L.Va[cur], *PW = L.W[cur];
+        int64_t ldp = am;
+        if (!rotated) {
             Seg2 vs, wsg;
             vs.X1 = L.Va[cur];
             vs.ld1 = am;
-            vs.p1 = kold;
+            vs.p1 = kr;
             wsg.X1 = L.W[cur];
             wsg.ld1 = am;
-            wsg.p1 = kold;
-            CD_TRY(update(vs, L.Y, am, 1.0, 0.0, L.Va[1 - cur], am, kact, n, st));
-            CD_TRY(update(wsg, L.Y, am, 1.0, 0.0, L.W[1 - cur], am, kact, n, st));
-            cur = 1 - cur;
+            wsg.p1 = kr;
+            CD_TRY(update(vs, L.Q[qc], am, 1.0, 0.0, T0, kb, nres, n, st));
+            CD_TRY(update(wsg, L.Q[qc], am, 1.0, 0.0, T1, kb, nres, n, st));
+            PV = T0;
+            PW = T1;
+            ldp = kb;
         }
-        // step 12: residuals of the first kb active pairs
-        const int nres = std::min(kb, kact);
-        CD_TRY(colnorms(L.W[cur], am, L.Va[cur], am, L.D, nres, n, L.res, L.part, st));
+        CD_TRY(colnorms(PW, ldp, PV, ldp, L.D, nres, n, L.res, L.part, st));
         CD_HIP(hipMemcpyAsync(h_vals, L.D, sizeof(double) * kact, hipMemcpyDeviceToHost, st));
         CD_HIP(hipMemcpyAsync(h_vals + am, L.res, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
         CD_HIP(hipStreamSynchronize(st));
@@ -284,20 +323,17 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         double min_open_res = INFINITY;
         for (int i = 0; i < nres; ++i)
             if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
+        int32_t *m_conv = h_map, *m_rest = h_map + am;
         if (ec) {
-            int32_t *m_conv = h_map, *m_rest = h_map + am;
             for (int t = 0; t < ec; ++t) m_conv[t] = conv[t];
             for (int t = 0; t < (int)rest.size(); ++t) m_rest[t] = rest[t];
             CD_HIP(hipMemcpyAsync(L.map, h_map, sizeof(int32_t) * 2 * am, hipMemcpyHostToDevice, st));
             // lock: append the converged Ritz vectors to Vl
-            CD_TRY(gather_cols(L.Va[cur], am, L.Vl + kc, r.lmax, L.map, ec, n, st));
+            CD_TRY(gather_cols(PV, ldp, L.Vl + kc, r.lmax, L.map, ec, n, st));
             for (int t = 0; t < ec; ++t) locked.push_back(D[conv[t]]);
             kc += ec;
-            // steps 12/14: the non-converged columns of V and W move to the front
-            if (!rest.empty()) {
-                CD_TRY(gather_cols(L.Va[cur], am, L.Va[cur], am, L.map + am, (int)rest.size(), n, st));
-                CD_TRY(gather_cols(L.W[cur], am, L.W[cur], am, L.map + am, (int)rest.size(), n, st));
-            }
+            // steps 12/14: the non-converged columns of Q move to the front
+            if (!rest.empty()) CD_TRY(gather_cols(L.Q[qc], am, L.Q[qc], am, L.map + am, (int)rest.size(), kr, st));
             kact -= ec;
         }
         // step 13
@@ -307,10 +343,12 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         }
         std::vector<double> Dact(kact);
         for (int t = 0; t < kact; ++t) Dact[t] = D[rest[t]];
-        // step 16: outer restart
-        if (ksub + kb > r.dim_max) {
+        // step 16: outer restart (ksub = kc + kact); B also rotated when it is full
+        if (kc + kact + kb > r.dim_max) {
             kact = r.dim_max - 2 * kb - kc;
-            ksub = kc + kact;
+            CD_TRY(compress(kact));
+        } else if (kr + kb > am) {
+            CD_TRY(compress(kact));
         }
         // step 15: H = diag of the retained non-converged Ritz values
         for (int t = 0; t < kact; ++t) h_diag[t] = Dact[t];
@@ -324,7 +362,13 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             const int n_ritz = std::min(kb - ec, kact);
             const int pad = kb - n_init - n_ritz;
             if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, L.Vtmp, kb, n_init, n, st)));
-            if (n_ritz) CD_TRY((copy_block<double, double>(L.Va[cur], am, L.Vtmp + n_init, kb, n_ritz, n, st)));
+            if (n_ritz) {
+                // the leading non-converged pairs are all among the first nres columns of PV
+                if (ec)
+                    CD_TRY(gather_cols(PV, ldp, L.Vtmp + n_init, kb, L.map + am, n_ritz, n, st));
+                else
+                    CD_TRY((copy_block<double, double>(PV, ldp, L.Vtmp + n_init, kb, n_ritz, n, st)));
+            }
             if (pad) {
                 CD_TRY(philox_fill(L.Vtmp + n_init + n_ritz, n, pad, kb, r.seed, next_col, st));
                 next_col += pad;

@@ -265,13 +265,15 @@ CONFIGS = {
 
 
 def make_config_graph(name: str, seed: int = DEFAULT_SEED, n_override=None):
-    """Edge list for a named workload.  Returns (edges, n_nodes, cfg)."""
+    """Edge list for a named workload.  Returns (edges, n_nodes, cfg); for SBM
+    workloads cfg["labels"] holds the planted block of every node."""
     cfg = dict(CONFIGS[name])
     n = int(n_override or cfg["n"])
     s = seed + cfg["seed_offset"]
     if cfg["kind"] == "sbm":
-        edges, _ = sbm(n, cfg["blocks"], p_in=cfg.get("p_in"), p_out=cfg.get("p_out"),
-                       d_in=cfg.get("d_in"), d_out=cfg.get("d_out"), uneven=cfg["uneven"], seed=s)
+        edges, labels = sbm(n, cfg["blocks"], p_in=cfg.get("p_in"), p_out=cfg.get("p_out"),
+                            d_in=cfg.get("d_in"), d_out=cfg.get("d_out"), uneven=cfg["uneven"], seed=s)
+        cfg["labels"] = labels
         return edges, n, cfg
     edges, n2 = chung_lu(n, gamma=cfg["gamma"], mean_degree=cfg["mean_degree"], seed=s)
     return edges, n2, cfg

@@ -22,7 +22,7 @@ def _check_eig(cd, H, tol_val=1e-12):
     assert np.linalg.norm(Y.T @ Y - np.eye(n), 2) <= 1e-13 * max(1, np.sqrt(n) / 4)
 
 
-@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 30, 64, 160, 320, 448])
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 16, 17, 30, 33, 64, 65, 97, 128, 129, 159, 160, 161, 320, 448])
 def test_random_symmetric(cd, dev, n):
     A = np.random.default_rng(n).standard_normal((n, n))
     print("case eig random n=%d" % n, flush=True)
@@ -42,7 +42,7 @@ def test_arrowhead(cd, dev, n, kb):
     _check_eig(cd, H)
 
 
-@pytest.mark.parametrize("n", [10, 100, 200])
+@pytest.mark.parametrize("n", [10, 100, 150, 200])
 def test_degenerate(cd, dev, n):
     rng = np.random.default_rng(n)
     Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
