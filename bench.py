@@ -72,19 +72,21 @@ def run_forms(cd, torch, g, cfg, forms, steps, warmup, seed):
         out[form] = dict(seconds=t, iterations=st["iterations"], n_spmm_filter=st["n_spmm_filter"],
                          n_spmm_filter_f32=st["n_spmm_filter_f32"], n_spmm_other=st["n_spmm_other"],
                          max_residual=st["max_residual"], filter_ms_per_launch=tf / max(nl, 1),
-                         filter_ms_per_solve=tf / steps, evals=r.evals.cpu().numpy())
+                         filter_ms_per_solve=tf / steps, evals=r.evals.cpu().numpy(), evecs=r.evecs)
         log("form %s: %.2f ms/solve, %d iterations, filter %.3f ms/solve (%.1f us/step), max res %.2e"
             % (form, 1e3 * t, st["iterations"], tf / steps, 1e3 * tf / max(nl, 1), st["max_residual"]))
+        del ws
+        torch.cuda.empty_cache()
     return out
 
 
-def warm_start_form(cd, torch, g, cfg, steps, seed):
+def warm_start_form(cd, torch, g, cfg, steps, seed, filter_dtype):
     """Solve started from the trained network (inference + Rayleigh-Ritz included)."""
     from paper_2212_04443_amd import gcn
     if not os.path.exists(gcn.WEIGHTS_FILE):
         return None
     net = gcn.Net.load()
-    p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed)
+    p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed, filter_dtype=filter_dtype)
     ws = torch.empty(cd.solve_workspace_size(g, p), dtype=torch.uint8, device="cuda")
     V0, _ = gcn.warm_start(g, net, seed=seed)
     cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
@@ -95,9 +97,38 @@ def warm_start_form(cd, torch, g, cfg, steps, seed):
         r = cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    log("form gcn-warm: %.2f ms/solve (inference included), %d iterations" % (1e3 * t, r.stats["iterations"]))
-    return dict(seconds=t, iterations=r.stats["iterations"], n_spmm_filter=r.stats["n_spmm_filter"],
-                max_residual=r.stats["max_residual"], evals=r.evals.cpu().numpy())
+    name = "gcn_warm_" + ("f64" if filter_dtype == cd.F64 else "f32")
+    log("form %s: %.2f ms/solve (inference included), %d iterations" % (name, 1e3 * t, r.stats["iterations"]))
+    out = dict(seconds=t, iterations=r.stats["iterations"], n_spmm_filter=r.stats["n_spmm_filter"],
+               max_residual=r.stats["max_residual"], evals=r.evals.cpu().numpy())
+    del ws, V0, r
+    torch.cuda.empty_cache()
+    return name, out
+
+
+def cluster_tail(cd, evecs, truth, k, seed):
+    """Clustering tail (row normalization + K-means) on the FP64 eigenvectors,
+    scored against the planted blocks."""
+    from paper_2212_04443_amd import spectral
+    cd.cluster(evecs, k, seed=seed)
+    torch_sync()
+    t0 = time.perf_counter()
+    labels, _, rounds, inertia = cd.cluster(evecs, k, seed=seed)
+    torch_sync()
+    t = time.perf_counter() - t0
+    lab = labels.cpu().numpy()
+    rec = dict(ms=1e3 * t, rounds=rounds, inertia=inertia)
+    if truth is not None:
+        rec["ari"] = spectral.adjusted_rand_index(lab, truth)
+        rec["nmi"] = spectral.normalized_mutual_info(lab, truth)
+    log("clustering tail: %.2f ms, %d rounds%s" % (rec["ms"], rounds,
+        ", ARI %.4f NMI %.4f" % (rec["ari"], rec["nmi"]) if truth is not None else ""))
+    return rec
+
+
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
 
 
 def measured_traffic(workload):
@@ -127,6 +158,16 @@ def copy_calibration():
     log("copied %d bytes" % (4 * n))
 
 
+def describe(name, n, nnz, cfg):
+    if cfg["kind"] == "sbm":
+        shape = "SBM n=%d, %d %s blocks, " % (n, cfg["blocks"], "uneven" if cfg["uneven"] else "equal")
+        shape += ("d_in=%g, d_out=%g" % (cfg["d_in"], cfg["d_out"]) if "d_in" in cfg
+                  else "p_in=%g, p_out=%g" % (cfg["p_in"], cfg["p_out"]))
+    else:
+        shape = "Chung-Lu n=%d (largest component), gamma=%g, mean degree %g" % (n, cfg["gamma"], cfg["mean_degree"])
+    return "%s: %s, nnz=%d; k=kb=%d, m=%d, tol=1e-8" % (name, shape, nnz, cfg["k"], cfg["m"])
+
+
 def cpu_baseline(edges, n, cfg, seed):
     import oracle
     oracle.build(force=False)
@@ -148,6 +189,8 @@ def main():
     ap.add_argument("--forms", default="f64,f32", help="comma list of f64,f32; the first is primary")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the GCN warm-start forms")
+    ap.add_argument("--no-cluster", action="store_true", help="skip the clustering tail")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -205,9 +248,7 @@ def main():
         "dtype": "f64" if forms[0] == "f64" else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "%s: SBM n=%d, %d uneven blocks, d_in=%g, d_out=%g, nnz=%d; k=kb=%d, m=%d, tol=1e-8"
-                        % (args.workload, n, cfg.get("blocks", 0), cfg.get("d_in", 0), cfg.get("d_out", 0),
-                           g.nnz, cfg["k"], cfg["m"]),
+            "workload": describe(args.workload, n, g.nnz, cfg),
             "form": forms[0],
             "seed": args.seed,
         },
@@ -227,16 +268,19 @@ def main():
         "max_residual": prim["max_residual"],
         "filter_gflops": flops_per_step(n, g.nnz, kb) / (prim["filter_ms_per_launch"] * 1e-3) / 1e9,
         "graph_build_ms": 1e3 * t_build,
-        "forms": {f: {k: (v if not isinstance(v, np.ndarray) else None) for k, v in r.items() if k != "evals"}
-                  for f, r in res.items()},
+        "forms": {f: {k: v for k, v in r.items() if k not in ("evals", "evecs")} for f, r in res.items()},
     }
     if len(forms) > 1:
         a, b2 = res[forms[0]]["evals"], res[forms[1]]["evals"]
         line["forms_max_dlambda"] = float(np.abs(a - b2).max())
-    ws_form = warm_start_form(cd, torch, g, cfg, args.steps, args.seed)
-    if ws_form is not None:
-        line["forms"]["gcn_warm_f64"] = {k: v for k, v in ws_form.items() if k != "evals"}
-        line["gcn_warm_max_dlambda"] = float(np.abs(ws_form["evals"] - prim["evals"]).max())
+    for fdt in ([cd.F64, cd.F32] if not args.no_warm_start else []):
+        wf = warm_start_form(cd, torch, g, cfg, args.steps, args.seed, fdt)
+        if wf is not None:
+            name, rec = wf
+            line["forms"][name] = {k: v for k, v in rec.items() if k != "evals"}
+            line[name + "_max_dlambda"] = float(np.abs(rec["evals"] - prim["evals"]).max())
+    if "f64" in res and not args.no_cluster:
+        line["cluster_tail"] = cluster_tail(cd, res["f64"]["evecs"], cfg.get("labels"), cfg["k"], args.seed)
     if not args.no_cpu_baseline:
         log("running the CPU oracle on the same workload ...")
         cb, ref = cpu_baseline(edges, n, cfg, args.seed)

@@ -284,8 +284,8 @@ chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *ev
  * labels: device int32[n] (output).  centres: device double, n_clusters x k,
  * row-major, leading dimension k (output).  rounds (host, nullable): Lloyd
  * rounds run.  inertia (host, nullable): sum over rows of the squared distance
- * to the assigned centre.  1 <= n_clusters <= min(n, 256) and n_clusters * k
- * <= 8000.  Workspace from chebdav_cluster_workspace_size.  Synchronizes the
+ * to the assigned centre.  1 <= n_clusters <= min(n, 256) and
+ * n_clusters * (k + 1) <= 8192.  Workspace from chebdav_cluster_workspace_size.  Synchronizes the
  * stream once per round.  Errors: EINVAL (sizes, NULL buffers, max_iter < 1),
  * ENOMEM (workspace too small), EUNSUPPORTED (n_clusters * k too large).
  * ------------------------------------------------------------------------ */

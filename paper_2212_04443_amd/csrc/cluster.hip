@@ -27,14 +27,16 @@ constexpr int kRowsTpb = 128;    // threads per block of the row kernels
 constexpr int kSplits = 1024;    // row ranges of the reductions
 
 // Squared distance; KP >= k is the padded width of the register copy of the row.
+// (The products and sums are kept separate: no contraction into fused multiply-add.)
 template <int KP>
 __device__ inline double sqd(const double (&f)[KP], const double *c, int k) {
+#pragma clang fp contract(off)
     double d = 0.0;
 #pragma unroll
     for (int j = 0; j < KP; ++j) {
         if (j < k) {
-            const double t = __dsub_rn(f[j], c[j]);
-            d = __dadd_rn(d, __dmul_rn(t, t));
+            const double t = f[j] - c[j];
+            d = d + t * t;
         }
     }
     return d;
@@ -47,15 +49,22 @@ __device__ inline void load_row(const double *__restrict__ F, int64_t i, int k, 
 }
 
 // F(i, :) = U(i, :) / ||U(i, :)||_2: one wavefront per row, lanes over columns.
+// Every lane forms the sum of squares itself, in ascending coordinate order
+// (entries passed lane to lane), then one rounded square root and division.
 __global__ void __launch_bounds__(256) k_row_normalize(const double *__restrict__ U, int64_t ldu, int64_t n,
                                                        int k, double *__restrict__ F) {
+#pragma clang fp contract(off)
     const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (r >= n) return;
     const int lane = lane_id();
     const double x = lane < k ? U[r * ldu + lane] : 0.0;
-    const double s = wave_sum(x * x);
-    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
-    if (lane < k) F[r * k + lane] = s > 0.0 ? x * inv : 0.0;
+    double s = 0.0;
+    for (int j = 0; j < k; ++j) {
+        const double xj = __shfl(x, j, kWave);
+        s = s + xj * xj;
+    }
+    const double nr = sqrt(s);
+    if (lane < k) F[r * k + lane] = nr > 0.0 ? x / nr : 0.0;
 }
 
 // Copy of row `idx` of F into centre slot c (idx read from the device).
@@ -139,13 +148,11 @@ __global__ void __launch_bounds__(256) k_ff_pick(const double *__restrict__ bval
 }
 
 // Assignment: label of every row = nearest centre (lower index among ties);
-// counts the rows whose label changed (integer atomics) and, if dist is not
-// NULL, stores the squared distance to the chosen centre.
+// counts the rows whose label changed (integer atomics).
 template <int KP>
 __global__ void __launch_bounds__(kRowsTpb) k_assign(const double *__restrict__ F, int64_t n, int k,
                                                      const double *__restrict__ C, int K,
-                                                     int32_t *__restrict__ labels, double *__restrict__ dist,
-                                                     int *__restrict__ changed) {
+                                                     int32_t *__restrict__ labels, int *__restrict__ changed) {
     extern __shared__ double cs[];  // K x k
     for (int e = threadIdx.x; e < K * k; e += blockDim.x) cs[e] = C[e];
     __syncthreads();
@@ -165,10 +172,23 @@ __global__ void __launch_bounds__(kRowsTpb) k_assign(const double *__restrict__ 
         }
         ch += labels[i] != bl;
         labels[i] = bl;
-        if (dist) dist[i] = best;
     }
     ch = wave_sum(ch);
     if (lane_id() == 0 && ch) atomicAdd(changed, ch);
+}
+
+// dist[i] = squared distance of row i to the centre it is labelled with.
+template <int KP>
+__global__ void __launch_bounds__(kRowsTpb) k_label_dist(const double *__restrict__ F, int64_t n, int k,
+                                                         const double *__restrict__ C,
+                                                         const int32_t *__restrict__ labels,
+                                                         double *__restrict__ dist) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double f[KP];
+        load_row<KP>(F, i, k, f);
+        dist[i] = sqd<KP>(f, C + (int64_t)labels[i] * k, k);
+    }
 }
 
 // Per row range z: sums of the rows of each cluster (lane j owns coordinate j,
@@ -207,20 +227,40 @@ __global__ void __launch_bounds__(kWave) k_centre_partial(const double *__restri
     for (int c = j; c < K; c += kWave) pcnt[(int64_t)blockIdx.x * K + c] = cnt[c];
 }
 
-// C(c, j) = (sum over splits in order) / count; an empty cluster keeps its centre.
+// C(c, j) = (sum of the split partials) / count; an empty cluster keeps its
+// centre.  Thread group zg of a block adds splits zg, zg + 8, ... for 32
+// entries; the eight group sums are added in order (fixed order overall).
 __global__ void __launch_bounds__(256) k_centre_final(const double *__restrict__ psum,
                                                       const int64_t *__restrict__ pcnt, int S, int K, int k,
                                                       double *__restrict__ C) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= K * k) return;
-    const int c = e / k;
-    double s = 0.0;
+    constexpr int EB = 32, ZG = 8;
+    __shared__ double sh[ZG][EB];
+    __shared__ int64_t shc[ZG][EB];
+    const int el = threadIdx.x % EB, zg = threadIdx.x / EB;
+    const int e = blockIdx.x * EB + el;
+    const int KK = K * k;
+    double sacc = 0.0;
     int64_t m = 0;
-    for (int z = 0; z < S; ++z) {
-        s += psum[(int64_t)z * K * k + e];
-        m += pcnt[(int64_t)z * K + c];
+    if (e < KK) {
+        const int c = e / k;
+        for (int z = zg; z < S; z += ZG) {
+            sacc += psum[(int64_t)z * KK + e];
+            m += pcnt[(int64_t)z * K + c];
+        }
     }
-    if (m > 0) C[e] = s / (double)m;
+    sh[zg][el] = sacc;
+    shc[zg][el] = m;
+    __syncthreads();
+    if (zg == 0 && e < KK) {
+        double t = 0.0;
+        int64_t mt = 0;
+#pragma unroll
+        for (int g = 0; g < ZG; ++g) {
+            t += sh[g][el];
+            mt += shc[g][el];
+        }
+        if (mt > 0) C[e] = t / (double)mt;
+    }
 }
 
 // Sum of dist over fixed row ranges, then in order.
@@ -282,12 +322,12 @@ ClusterWs cluster_layout(Arena &a, int64_t n, int k, int K) {
 }
 
 chebdav_status assign(int KP, int B, size_t lds, const double *F, int64_t n, int k, const double *C, int K,
-                      int32_t *labels, double *dist, int *changed, hipStream_t st) {
+                      int32_t *labels, int *changed, hipStream_t st) {
     switch (KP) {
-        case 8: hipLaunchKernelGGL(k_assign<8>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, dist, changed); break;
-        case 16: hipLaunchKernelGGL(k_assign<16>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, dist, changed); break;
-        case 32: hipLaunchKernelGGL(k_assign<32>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, dist, changed); break;
-        default: hipLaunchKernelGGL(k_assign<64>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, dist, changed); break;
+        case 8: hipLaunchKernelGGL(k_assign<8>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, changed); break;
+        case 16: hipLaunchKernelGGL(k_assign<16>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, changed); break;
+        case 32: hipLaunchKernelGGL(k_assign<32>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, changed); break;
+        default: hipLaunchKernelGGL(k_assign<64>, dim3(B), dim3(kRowsTpb), lds, st, F, n, k, C, K, labels, changed); break;
     }
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
@@ -325,7 +365,7 @@ chebdav_status cluster(const double *U, int64_t ldu, int64_t n, int k, int K, in
     if (!hchg) return fail(CHEBDAV_ENOMEM, "pinned host allocation failed");
     const size_t lds_assign = sizeof(double) * (size_t)K * k;
     const size_t lds_partial = sizeof(double) * (size_t)K * k + sizeof(int64_t) * K;
-    if (lds_partial > 64 * 1024) return fail(CHEBDAV_EUNSUPPORTED, "n_clusters * k too large (K k <= 8000)");
+    if (lds_partial > 64 * 1024) return fail(CHEBDAV_EUNSUPPORTED, "n_clusters * (k + 1) must be <= 8192");
     const int KP = k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 64;
 
     // step 3: row normalization
@@ -360,20 +400,25 @@ chebdav_status cluster(const double *U, int64_t ldu, int64_t n, int k, int K, in
     while (r < max_iter) {
         ++r;
         CD_HIP(hipMemsetAsync(s.changed, 0, sizeof(int), st));
-        CD_TRY(assign(KP, B, lds_assign, s.F, n, k, centres, K, labels, nullptr, s.changed, st));
+        CD_TRY(assign(KP, B, lds_assign, s.F, n, k, centres, K, labels, s.changed, st));
         hipLaunchKernelGGL(k_centre_partial, dim3(S), dim3(kWave), lds_partial, st, s.F, n, k, labels, K, rps,
                            s.psum, s.pcnt);
         CD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_centre_final, dim3((unsigned)ceil_div(K * k, 256)), dim3(256), 0, st, s.psum, s.pcnt,
+        hipLaunchKernelGGL(k_centre_final, dim3((unsigned)ceil_div(K * k, 32)), dim3(256), 0, st, s.psum, s.pcnt,
                            S, K, k, centres);
         CD_LAUNCH_CHECK();
         CD_HIP(hipMemcpyAsync(hchg, s.changed, sizeof(int), hipMemcpyDeviceToHost, st));
         CD_HIP(hipStreamSynchronize(st));
         if (*hchg == 0) break;
     }
-    // inertia of the final assignment to the final centres
-    CD_HIP(hipMemsetAsync(s.changed, 0, sizeof(int), st));
-    CD_TRY(assign(KP, B, lds_assign, s.F, n, k, centres, K, labels, s.mind, s.changed, st));
+    // inertia: squared distances of the rows to the final centres of their labels
+    switch (KP) {
+        case 8: hipLaunchKernelGGL(k_label_dist<8>, dim3(B), dim3(kRowsTpb), 0, st, s.F, n, k, centres, labels, s.mind); break;
+        case 16: hipLaunchKernelGGL(k_label_dist<16>, dim3(B), dim3(kRowsTpb), 0, st, s.F, n, k, centres, labels, s.mind); break;
+        case 32: hipLaunchKernelGGL(k_label_dist<32>, dim3(B), dim3(kRowsTpb), 0, st, s.F, n, k, centres, labels, s.mind); break;
+        default: hipLaunchKernelGGL(k_label_dist<64>, dim3(B), dim3(kRowsTpb), 0, st, s.F, n, k, centres, labels, s.mind); break;
+    }
+    CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_partial, dim3(S), dim3(256), 0, st, s.mind, n, rps, s.dsum);
     CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(64), 0, st, s.dsum, S, s.out);

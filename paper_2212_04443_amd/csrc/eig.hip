@@ -1,7 +1,7 @@
 // Symmetric eigendecomposition H = Y diag(w) Y^T of the small Rayleigh-quotient
 // matrix (Alg. 2 step 9), ascending.  Pipeline:
 //   1. Householder tridiagonalization Q^T H Q = T (one workgroup; the working
-//      matrix in LDS up to n = 128, else in L2; the Householder vector in LDS);
+//      matrix in LDS up to n = 128, in registers up to n = 160, else in L2);
 //   2. eigenvalues of T by multisection on Sturm counts, one wavefront per
 //      eigenvalue (64 points per round);
 //   3. eigenvectors of T by inverse iteration with the LU factorization (with
@@ -21,6 +21,7 @@ namespace {
 
 constexpr int kMaxN = 1024;
 constexpr int kLdsMaxN = 128;  // working matrix in LDS (n^2 doubles) up to this size
+constexpr int kRegMaxN = 160;  // working matrix in registers for kLdsMaxN < n <= kRegMaxN
 constexpr double kEps = DBL_EPSILON * 0.5;
 constexpr double kTightRel = 1e-6;
 
@@ -555,20 +556,9 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
     EigWs s = eig_layout(a, n);
-    if (n <= 160) {
-        const int T = 2 * (int)ceil_div(n, 32);
-#define CD_TRI(TT)                                                                                   \
-    case TT:                                                                                         \
-        hipLaunchKernelGGL(k_tridiag_reg<TT>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); \
-        break;
-        switch (T) {
-            CD_TRI(2)
-            CD_TRI(4)
-            CD_TRI(6)
-            CD_TRI(8)
-            CD_TRI(10)
-        }
-#undef CD_TRI
+    if (n > kLdsMaxN && n <= kRegMaxN) {
+        hipLaunchKernelGGL(k_tridiag_reg<kRegMaxN / 16>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e,
+                           s.tau);
     } else if (n <= kLdsMaxN)
         hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(512), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
     else

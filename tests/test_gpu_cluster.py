@@ -42,6 +42,8 @@ def _compare(cd, ocl, U, K, seed, max_iter=100):
 def test_cluster_matches_oracle(cd, ocl, dev, n, k, K, seed):
     rng = np.random.default_rng(seed)
     centres = rng.standard_normal((K, k))
+    if k == 1:  # one coordinate normalizes to +-1: keep both signs present
+        centres = np.where(np.arange(K)[:, None] % 2 == 0, 1.0, -1.0)
     truth = rng.integers(0, K, n)
     U = centres[truth] * rng.uniform(0.5, 2.0, (n, 1)) + 0.05 * rng.standard_normal((n, k))
     print("case cluster n=%d k=%d K=%d" % (n, k, K), flush=True)
