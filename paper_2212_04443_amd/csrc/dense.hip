@@ -32,10 +32,11 @@ __device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
 }
 
 // Partial Gram on matrix cores: one wavefront computes the 64 x (16 TQT) tile
-// (i0.., j0..) of Xs^T Y over the rows of split z, four rows per MFMA step, with
-// both operands loaded straight from the row-major blocks (lane k*16 + c reads
+// (i0.., j0..) of Xs^T Y over the rows of split z, four rows per MFMA step and
+// 4 UR rows per loop trip (all their loads issued before the MFMAs), with both
+// operands loaded straight from the row-major blocks (lane k*16 + c reads
 // column c of row k: four 128-byte row segments per load).
-template <int TQT>
+template <int TQT, int UR>
 __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy, int q,
                                              int64_t n, int64_t rows_per_split, double *__restrict__ part) {
     const int p = xs.cols();
@@ -54,10 +55,10 @@ __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__
     for (int t = 0; t < 4; ++t) colv[t] = i0 + 16 * t + cc < p;
 #pragma unroll
     for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
-    for (int64_t r = r_beg; r < r_end; r += 8) {
-        double a[2][4], b[2][TQT];
+    for (int64_t r = r_beg; r < r_end; r += 4 * UR) {
+        double a[UR][4], b[UR][TQT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < UR; ++h) {
             const int64_t row = r + 4 * h + kr;
             const bool rv = row < r_end;
 #pragma unroll
@@ -66,7 +67,7 @@ __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__
             for (int u = 0; u < TQT; ++u) b[h][u] = (rv && colw[u]) ? Y[row * ldy + j0 + 16 * u + cc] : 0.0;
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < UR; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -84,20 +85,30 @@ __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__
             }
 }
 
-// Fixed-order reduction of S partial arrays of E elements: thread group zg sums
-// z = zg, zg + 8, ... and the eight group sums are added in order.
+// Fixed-order reduction of S partial arrays of E elements.  A block owns EB
+// consecutive elements; thread group zg (ZG groups) adds splits z = zg, zg + ZG,
+// ... into four accumulators (z mod 4 ZG), combined as (a0 + a1) + (a2 + a3);
+// the ZG group sums are then added in order.  The order depends only on S.
 // MODE 0 writes C[(e / q) * ldc + e % q] (a Gram tile); MODE 1 writes sqrt(sum) to C[e].
 template <int MODE>
 __global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part, int S, int64_t E, int q,
                                                 double *__restrict__ C, int64_t ldc) {
-    constexpr int EB = 32, ZG = 8;
+    constexpr int EB = 8, ZG = 32;
     __shared__ double sh[ZG][EB];
     const int el = threadIdx.x % EB, zg = threadIdx.x / EB;
     const int64_t e = (int64_t)blockIdx.x * EB + el;
-    double s = 0.0;
-    if (e < E)
-        for (int z = zg; z < S; z += ZG) s += part[(int64_t)z * E + e];
-    sh[zg][el] = s;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e < E) {
+        int z = zg;
+        for (; z + 3 * ZG < S; z += 4 * ZG) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += part[(int64_t)(z + u * ZG) * E + e];
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+            if (z + u * ZG < S) a[u] += part[(int64_t)(z + u * ZG) * E + e];
+    }
+    sh[zg][el] = (a[0] + a[1]) + (a[2] + a[3]);
     __syncthreads();
     if (zg == 0 && e < E) {
         double t = 0.0;
@@ -110,20 +121,20 @@ __global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part,
     }
 }
 
-// Row splits of a Gram product: about 1024 wavefronts in total, at least 512 rows each.
+// Row splits of a Gram product: about 2048 wavefronts in total, at least 256 rows each.
 int gram_splits(int64_t n, int p, int q) {
     const int tiles = (int)(ceil_div(p, TB) * ceil_div(q, TB));
-    int64_t s = std::max<int64_t>(1, 1024 / tiles);
-    s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n, 512)));
+    int64_t s = std::max<int64_t>(1, 2048 / tiles);
+    s = std::min<int64_t>(s, std::max<int64_t>(1, ceil_div(n, 256)));
     return (int)s;
 }
 
 // Y = alpha Xs B + beta Y on matrix cores: one wavefront owns a 64-row x
 // (16 TQT)-column tile of Y, accumulates over all p columns of Xs (four per MFMA
 // step; lane k*16 + i reads row i, column k: consecutive lanes of a row read
-// adjacent elements) and writes the tile only at the end, so Y may alias Xs when
-// it has a single column tile.
-template <int TQT>
+// adjacent elements; 4 UR columns per loop trip) and writes the tile only at
+// the end, so Y may alias Xs when it has a single column tile.
+template <int TQT, int UR>
 __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
                                                double alpha, double beta, double *Y, int64_t ldy, int q,
                                                int64_t n) {
@@ -142,10 +153,10 @@ __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict
     for (int t = 0; t < 4; ++t) rowv[t] = r0 + 16 * t + cc < n;
 #pragma unroll
     for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
-    for (int k0 = 0; k0 < p; k0 += 8) {
-        double a[2][4], b[2][TQT];
+    for (int k0 = 0; k0 < p; k0 += 4 * UR) {
+        double a[UR][4], b[UR][TQT];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < UR; ++h) {
             const int kk = k0 + 4 * h + kr;
             const bool kv = kk < p;
 #pragma unroll
@@ -154,7 +165,7 @@ __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict
             for (int u = 0; u < TQT; ++u) b[h][u] = (kv && colw[u]) ? B[(int64_t)kk * ldb + j0 + 16 * u + cc] : 0.0;
         }
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
+        for (int h = 0; h < UR; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -277,8 +288,8 @@ unsigned grid_for(int64_t total) {
 
 }  // namespace
 
-// Upper bound of splits * p' * q' over all p' <= p, q' <= q: splits * tiles <=
-// max(tiles, 2048) and p' q' <= tiles * TB * TB.
+// Upper bound of splits * p' * q' over all p' <= p, q' <= q: splits * tiles' <=
+// max(tiles', 2048) <= max(tiles, 2048) and p' q' <= tiles' * TB * TB.
 size_t gram_partial_elems(int64_t, int p, int q) {
     const int64_t tiles = ceil_div(std::max(p, 1), TB) * ceil_div(std::max(q, 1), TB);
     return (size_t)std::max<int64_t>(tiles, 2048) * TB * TB;
@@ -289,18 +300,18 @@ chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t
     const int p = Xs.cols();
     if (p == 0 || q == 0) return CHEBDAV_OK;
     const int splits = gram_splits(n, p, q);
-    const int64_t rps = ceil_div(ceil_div(n, splits), 8) * 8;
+    const int64_t rps = ceil_div(ceil_div(n, splits), 16) * 16;
     const int qt = std::min(q, TB);
     const dim3 grid((unsigned)ceil_div(p, TB), (unsigned)ceil_div(q, qt), (unsigned)splits);
     if (qt <= 16)
-        hipLaunchKernelGGL(k_gram<1>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        hipLaunchKernelGGL((k_gram<1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
     else if (qt <= 32)
-        hipLaunchKernelGGL(k_gram<2>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        hipLaunchKernelGGL((k_gram<2, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
     else
-        hipLaunchKernelGGL(k_gram<4>, grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        hipLaunchKernelGGL((k_gram<4, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
     CD_LAUNCH_CHECK();
     const int64_t pq = (int64_t)p * q;
-    hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 32)), dim3(256), 0, st, partial, splits, pq,
+    hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 8)), dim3(256), 0, st, partial, splits, pq,
                        q, C, ldc);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
@@ -317,12 +328,23 @@ chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha
     }
     const int qt = std::min(q, TB);
     const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, qt));
-    if (qt <= 16)
-        hipLaunchKernelGGL(k_update<1>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    else if (qt <= 32)
-        hipLaunchKernelGGL(k_update<2>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    else
-        hipLaunchKernelGGL(k_update<4>, grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    const bool deep = Xs.cols() >= 64;  // longer sums: 32 columns per loop trip
+    if (qt <= 16) {
+        if (deep)
+            hipLaunchKernelGGL((k_update<1, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+        else
+            hipLaunchKernelGGL((k_update<1, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    } else if (qt <= 32) {
+        if (deep)
+            hipLaunchKernelGGL((k_update<2, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+        else
+            hipLaunchKernelGGL((k_update<2, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    } else {
+        if (deep)
+            hipLaunchKernelGGL((k_update<4, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+        else
+            hipLaunchKernelGGL((k_update<4, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    }
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
@@ -340,7 +362,7 @@ chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t l
         hipLaunchKernelGGL(k_colnorm, dim3(blocks), dim3(NT), 0, st, X + c0, ldx, Y ? Y + c0 : nullptr,
                            ldy, theta ? theta + c0 : nullptr, pw, n, rpb, partial);
         CD_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_reduce<1>, dim3((unsigned)ceil_div(pw, 32)), dim3(256), 0, st, partial, blocks,
+        hipLaunchKernelGGL(k_reduce<1>, dim3((unsigned)ceil_div(pw, 8)), dim3(256), 0, st, partial, blocks,
                            (int64_t)pw, 1, out + c0, 1);
         CD_LAUNCH_CHECK();
     }
