@@ -264,6 +264,28 @@ chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *ev
                                  int64_t ldy, void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Spectrum bounds by Lanczos (Sec. 2: when the filter's bounds are unknown,
+ * a few Lanczos steps estimate them).
+ *
+ * Plain Lanczos on A without reorthogonalization, from Philox column
+ * 2^32 - 1 of the seed (counter (row, row >> 32, 2^32 - 1, 0), the generator of
+ * chebdav_philox_fill) scaled to unit length:
+ *   w = A v_j - beta_{j-1} v_{j-1}; alpha_j = v_j . w; w -= alpha_j v_j;
+ *   beta_j = ||w||_2; v_{j+1} = w / beta_j,
+ * for at most `steps` steps (1..256), stopping when beta_j <= 1e-12 max(1, |alpha_j|).
+ * lower / upper (host) = min / max Ritz value of the tridiagonal T_k -/+ beta_k
+ * (Zhou & Li, 2011); for the normalized Laplacian the analytic interval is [0, 2].
+ * alpha, beta (host, nullable, `steps` entries) receive the recurrence
+ * coefficients; steps_done (host, nullable) the number of steps run.
+ * Synchronizes the stream after every step.  Errors: EINVAL (steps outside
+ * 1..256, NULL lower/upper), ENOMEM (workspace), EBREAKDOWN (non-finite values).
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_lanczos_bounds_workspace_size(const chebdav_graph *g, int steps, size_t *bytes);
+chebdav_status chebdav_lanczos_bounds(const chebdav_graph *g, int steps, uint64_t seed, double *lower,
+                                      double *upper, double *alpha, double *beta, int *steps_done,
+                                      void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Clustering tail of spectral clustering (Alg. 1, steps 3-4).
  *
  * Row normalization of the eigenvector block, then Lloyd's K-means:

@@ -36,6 +36,7 @@ EXPORTED = [
     "chebdav_subspace_loss_workspace_size", "chebdav_subspace_loss", "chebdav_adam_step",
     "chebdav_rayleigh_ritz_workspace_size", "chebdav_rayleigh_ritz",
     "chebdav_cluster_workspace_size", "chebdav_cluster",
+    "chebdav_lanczos_bounds_workspace_size", "chebdav_lanczos_bounds",
 ]
 
 
@@ -101,6 +102,8 @@ def _load():
         "chebdav_rayleigh_ritz": [p, p, i64, i32, u64, p, i64, p, p, sz, p],
         "chebdav_cluster_workspace_size": [i64, i32, i32, P(sz)],
         "chebdav_cluster": [p, i64, i64, i32, i32, i32, u64, p, p, P(i32), P(d), p, sz, p],
+        "chebdav_lanczos_bounds_workspace_size": [p, i32, P(sz)],
+        "chebdav_lanczos_bounds": [p, i32, u64, P(d), P(d), P(d), P(d), P(i32), p, sz, p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -412,3 +415,18 @@ def cluster(U: torch.Tensor, n_clusters: int, seed: int = 0, max_iter: int = 100
                                 ctypes.byref(rounds), ctypes.byref(inertia), _ptr(ws), ws.numel(),
                                 _stream(stream)))
     return labels, C, rounds.value, inertia.value
+
+
+def lanczos_bounds(g: Graph, steps: int = 10, seed: int = 0, stream=None):
+    """chebdav_lanczos_bounds: (lower, upper, alpha, beta) from `steps` Lanczos steps."""
+    import numpy as np
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_lanczos_bounds_workspace_size(g.handle, steps, ctypes.byref(nb)))
+    ws = _workspace(nb.value, "cuda")
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    al = (ctypes.c_double * steps)()
+    be = (ctypes.c_double * steps)()
+    k = ctypes.c_int()
+    _check(_lib.chebdav_lanczos_bounds(g.handle, steps, seed, ctypes.byref(lo), ctypes.byref(hi), al, be,
+                                       ctypes.byref(k), _ptr(ws), ws.numel(), _stream(stream)))
+    return lo.value, hi.value, np.array(al[:k.value]), np.array(be[:k.value])

@@ -201,6 +201,20 @@ chebdav_status chebdav_small_eig(const double *H, int64_t ldh, int n, double *ev
     return small_eig(H, ldh, n, evals, evecs, ldy, workspace, ws_bytes, as_stream(hip_stream));
 }
 
+chebdav_status chebdav_lanczos_bounds_workspace_size(const chebdav_graph *g, int steps, size_t *bytes) {
+    CHECK_GRAPH(g);
+    if (!bytes) return fail(CHEBDAV_EINVAL, "bytes is NULL");
+    return lanczos_ws_bytes(g->g->n, steps, bytes);
+}
+
+chebdav_status chebdav_lanczos_bounds(const chebdav_graph *g, int steps, uint64_t seed, double *lower,
+                                      double *upper, double *alpha, double *beta, int *steps_done,
+                                      void *workspace, size_t ws_bytes, void *hip_stream) {
+    CHECK_GRAPH(g);
+    return lanczos_bounds(g->g, steps, seed, lower, upper, alpha, beta, steps_done, workspace, ws_bytes,
+                          as_stream(hip_stream));
+}
+
 chebdav_status chebdav_cluster_workspace_size(int64_t n, int k, int n_clusters, size_t *bytes) {
     if (!bytes) return fail(CHEBDAV_EINVAL, "bytes is NULL");
     return cluster_ws_bytes(n, k, n_clusters, bytes);

@@ -29,6 +29,42 @@ __device__ inline T wave_sum(T v) {
     return v;
 }
 
+// Data-parallel-primitive move of a double within rows of 16 lanes (both
+// 32-bit halves with the same control; every lane of the wavefront active).
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ inline double read_lane(double v, int lane) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Sum over each row of 16 lanes (lanes 16r .. 16r + 15), the same value in
+// every lane of the row: rotations by 8, 4, 2, 1.  Every lane must be active.
+__device__ inline double row16_sum(double v) {
+    v += dpp_move<0x128>(v);  // row_ror:8
+    v += dpp_move<0x124>(v);  // row_ror:4
+    v += dpp_move<0x122>(v);  // row_ror:2
+    v += dpp_move<0x121>(v);  // row_ror:1
+    return v;
+}
+
+// Sum over the wavefront, the same value in every lane, in a fixed order: row
+// rotations by 8, 4, 2, 1 give every lane its 16-lane row's sum, then the four
+// row sums are added as (r0 + r1) + (r2 + r3).  Every lane must be active.
+template <>
+__device__ inline double wave_sum<double>(double v) {
+    v = row16_sum(v);
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
 // Exclusive scan over the block (blockDim.x a multiple of 64, <= 1024).
 // `total` receives the block sum.  Contains __syncthreads(): call from all threads.
 template <typename T>

@@ -1,7 +1,7 @@
 // Symmetric eigendecomposition H = Y diag(w) Y^T of the small Rayleigh-quotient
 // matrix (Alg. 2 step 9), ascending.  Pipeline:
 //   1. Householder tridiagonalization Q^T H Q = T (one workgroup; the working
-//      matrix in LDS up to n = 128, in registers up to n = 160, else in L2);
+//      matrix in registers up to n = 160, else in L2);
 //   2. eigenvalues of T by multisection on Sturm counts, one wavefront per
 //      eigenvalue (64 points per round);
 //   3. eigenvectors of T by inverse iteration with the LU factorization (with
@@ -20,8 +20,7 @@ namespace chebdav {
 namespace {
 
 constexpr int kMaxN = 1024;
-constexpr int kLdsMaxN = 128;  // working matrix in LDS (n^2 doubles) up to this size
-constexpr int kRegMaxN = 160;  // working matrix in registers for kLdsMaxN < n <= kRegMaxN
+constexpr int kRegMaxN = 160;  // working matrix in registers up to this size
 constexpr double kEps = DBL_EPSILON * 0.5;
 constexpr double kTightRel = 1e-6;
 
@@ -136,15 +135,6 @@ __device__ __forceinline__ void tridiag_run(double *A, const double *__restrict_
     }
 }
 
-// Working matrix in LDS (n <= kLdsMaxN).
-__global__ void __launch_bounds__(512) k_tridiag_lds(const double *__restrict__ H, int64_t ldh, int n,
-                                                     double *__restrict__ Vh, double *__restrict__ d,
-                                                     double *__restrict__ e, double *__restrict__ tau) {
-    __shared__ double As[kLdsMaxN * kLdsMaxN];
-    __shared__ double v[kLdsMaxN], wsh[kLdsMaxN], red[512];
-    tridiag_run(As, H, ldh, n, Vh, d, e, tau, v, wsh, red);
-}
-
 // Working matrix in global memory (L2-resident), any n <= kMaxN.
 __global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, int64_t ldh, int n,
                                                  double *Ag, double *__restrict__ Vh, double *__restrict__ d,
@@ -154,18 +144,21 @@ __global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, i
 }
 
 // Register-resident variant for n <= 16 T: the working matrix is spread over a
-// 16 x 16 thread grid, thread (pr, pc) holding A(pr + 16 a, pc + 16 b) for a, b < T,
-// so the product A v and the rank-2 update touch no shared memory; only the
-// vectors (column k, v, p, w) go through LDS, and the sums over the column index
-// are lane shuffles inside 16-lane groups.  Tiles whose rows (or columns) all lie
-// in the finished leading part are skipped (uniform branches).
+// 16 x 16 thread grid, thread (pc, pr) = (tid / 16, tid % 16) holding
+// A(pr + 16 a, pc + 16 b) for a, b < T, so a row group of 16 lanes (one pc) owns
+// whole columns.  A step k then needs two barriers: the row group that owns
+// column k forms the reflector from its registers (sums over its 16 lanes by
+// DPP row rotations) and publishes v; every thread forms its column sums of
+// A v (row rotations again; A is symmetric, so column sums are p), the row
+// groups publish p and their share of p^T v; every thread then updates its
+// entries.  Tiles whose rows or columns are all finished are skipped.
 template <int T>
 __global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ H, int64_t ldh, int n,
                                                      double *__restrict__ Vh, double *__restrict__ d,
                                                      double *__restrict__ e, double *__restrict__ tau) {
     constexpr int P = 16, NV = P * T;
-    __shared__ double xs[NV], vs[NV], ws[NV], scal[2];
-    const int tid = threadIdx.x, pr = tid / P, pc = tid % P;
+    __shared__ double vs[NV], ps[NV], kp[P], scal[2];
+    const int tid = threadIdx.x, pc = tid / P, pr = tid % P;
     double A[T][T];
 #pragma unroll
     for (int a = 0; a < T; ++a)
@@ -175,86 +168,91 @@ __global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ 
             A[a][b] = (i < n && j < n) ? H[(int64_t)i * ldh + j] : 0.0;
         }
     for (int k = 0; k + 2 < n; ++k) {
-        const int m = n - k - 1;
-        // column k (rows k..n-1) into xs
         if (pc == k % P) {
+            // column k of the working matrix, rows pr + 16 a
             const int bk = k / P;
+            double col[T];
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                double v = 0.0;
+#pragma unroll
+                for (int b = 0; b < T; ++b) v = (b == bk) ? A[a][b] : v;
+                col[a] = v;
+            }
+            double part = 0.0, x0 = 0.0, dk = 0.0;
 #pragma unroll
             for (int a = 0; a < T; ++a) {
                 const int i = pr + P * a;
-                double val = 0.0;
-#pragma unroll
-                for (int b = 0; b < T; ++b) val = (b == bk) ? A[a][b] : val;
-                if (i >= k && i < n) xs[i] = val;
+                if (i > k + 1 && i < n) part += col[a] * col[a];
+                if (i == k + 1) x0 = col[a];
+                if (i == k) dk = col[a];
             }
-        }
-        __syncthreads();
-        // reflector (wavefront 0): v = x - alpha e1 in vs (zero outside rows k+1..n-1)
-        if (tid < kWave) {
-            double part = 0.0;
-            for (int i = k + 2 + tid; i < n; i += kWave) part += xs[i] * xs[i];
-            const double ss = wave_sum(part);
-            const double x0 = xs[k + 1];
+            const double ss = row16_sum(part);
+            x0 = row16_sum(x0);  // one lane holds it, the others add zeros
+            dk = row16_sum(dk);
             double t = 0.0, v0 = 0.0, alpha = x0;
             if (ss != 0.0) {
                 alpha = -copysign(sqrt(x0 * x0 + ss), x0);
                 v0 = x0 - alpha;
                 t = 2.0 / (v0 * v0 + ss);
             }
-            for (int i = tid; i < NV; i += kWave) {
+#pragma unroll
+            for (int a = 0; a < T; ++a) {
+                const int i = pr + P * a;
                 double v = 0.0;
-                if (t != 0.0 && i > k && i < n) v = (i == k + 1) ? v0 : xs[i];
+                if (t != 0.0 && i > k && i < n) v = (i == k + 1) ? v0 : col[a];
                 vs[i] = v;
                 if (i > k && i < n) Vh[(int64_t)k * n + (i - k - 1)] = v;
             }
-            if (tid == 0) {
+            if (pr == 0) {
                 scal[0] = t;
                 tau[k] = t;
                 e[k] = alpha;
-                d[k] = xs[k];
+                d[k] = dk;
             }
         }
         __syncthreads();
         const double t = scal[0];
-        if (t != 0.0) {
-            // p = t A v: partial sums over this thread's columns, then over the 16 lanes of the row group
-            double vc[T];
-#pragma unroll
-            for (int b = 0; b < T; ++b) vc[b] = vs[pc + P * b];
-#pragma unroll
-            for (int a = 0; a < T; ++a) {
-                if (P * (a + 1) - 1 <= k) continue;  // rows of this tile are all finished
-                double sacc = 0.0;
-#pragma unroll
-                for (int b = 0; b < T; ++b)
-                    if (P * (b + 1) - 1 > k) sacc += A[a][b] * vc[b];
-#pragma unroll
-                for (int o = P / 2; o > 0; o >>= 1) sacc += __shfl_xor(sacc, o, P);
-                if (pc == 0) xs[pr + P * a] = t * sacc;
-            }
-            __syncthreads();
-            // w = p - (t/2)(p^T v) v (wavefront 0)
-            if (tid < kWave) {
-                double part = 0.0;
-                for (int i = k + 1 + tid; i < n; i += kWave) part += xs[i] * vs[i];
-                const double K = 0.5 * t * wave_sum(part);
-                for (int i = tid; i < NV; i += kWave) ws[i] = (i > k && i < n) ? xs[i] - K * vs[i] : 0.0;
-            }
-            __syncthreads();
-            // A <- A - v w^T - w v^T
-            double wc[T];
-#pragma unroll
-            for (int b = 0; b < T; ++b) wc[b] = ws[pc + P * b];
-#pragma unroll
-            for (int a = 0; a < T; ++a) {
-                if (P * (a + 1) - 1 <= k) continue;
-                const double vr = vs[pr + P * a], wr = ws[pr + P * a];
-#pragma unroll
-                for (int b = 0; b < T; ++b)
-                    if (P * (b + 1) - 1 > k) A[a][b] -= vr * wc[b] + wr * vc[b];
-            }
+        if (t == 0.0) {  // uniform: the reflector is the identity
+            __syncthreads();  // everyone has read scal before the next step rewrites it
+            continue;
         }
-        (void)m;
+        double vr[T], vc[T], q[T];
+#pragma unroll
+        for (int a = 0; a < T; ++a) vr[a] = vs[pr + P * a];
+#pragma unroll
+        for (int b = 0; b < T; ++b) vc[b] = vs[pc + P * b];
+        // p_j = t sum_i A(i, j) v_i for this row group's columns j = pc + 16 b
+        double kpart = 0.0;
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            q[b] = 0.0;
+            if (P * (b + 1) - 1 <= k) continue;  // columns of this tile are all finished
+            double sacc = 0.0;
+#pragma unroll
+            for (int a = 0; a < T; ++a)
+                if (P * (a + 1) - 1 > k) sacc += A[a][b] * vr[a];
+            q[b] = t * row16_sum(sacc);
+            kpart += q[b] * vc[b];
+        }
+#pragma unroll
+        for (int b = 0; b < T; ++b)
+            if (pr == b) ps[pc + P * b] = q[b];
+        if (pr == 0) kp[pc] = kpart;
+        __syncthreads();
+        // w = p - (t/2)(p^T v) v;  A <- A - v w^T - w v^T
+        double ktot = 0.0;
+#pragma unroll
+        for (int g = 0; g < P; ++g) ktot += kp[g];
+        const double K = 0.5 * t * ktot;
+#pragma unroll
+        for (int a = 0; a < T; ++a) {
+            if (P * (a + 1) - 1 <= k) continue;
+            const double wr = ps[pr + P * a] - K * vr[a];
+#pragma unroll
+            for (int b = 0; b < T; ++b)
+                if (P * (b + 1) - 1 > k) A[a][b] -= vr[a] * (q[b] - K * vc[b]) + wr * vc[b];
+        }
     }
     // trailing 2 x 2 block (or the 1 x 1 matrix)
 #pragma unroll
@@ -276,6 +274,13 @@ __global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ 
         }
 }
 
+// 1/q from the hardware reciprocal refined by one Newton step (relative error
+// a few units in the last place: enough for a backward-stable Sturm count).
+__device__ inline double recip(double q) {
+    const double r = __builtin_amdgcn_rcp(q);
+    return fma(r, fma(-q, r, 1.0), r);
+}
+
 // Number of eigenvalues of T smaller than x (Sturm sequence).
 __device__ inline int sturm(const double *d, const double *e, int n, double x, double pivmin) {
     int c = 0;
@@ -283,7 +288,7 @@ __device__ inline int sturm(const double *d, const double *e, int n, double x, d
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
     for (int i = 1; i < n; ++i) {
-        q = d[i] - x - e[i - 1] * e[i - 1] / q;
+        q = d[i] - x - (e[i - 1] * e[i - 1]) * recip(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
@@ -363,7 +368,7 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
                                                 const double *__restrict__ par, double *__restrict__ Zv) {
     extern __shared__ double sm[];
     double *dl = sm, *dd = sm + n, *du = sm + 2 * n, *du2 = sm + 3 * n, *x = sm + 4 * n;
-    int *ipiv = reinterpret_cast<int *>(sm + 5 * n);
+    int *ipiv = reinterpret_cast<int *>(sm + 6 * n);
     const int j = blockIdx.x;
     const int lane = lane_id();
     if (n == 1) {
@@ -385,49 +390,67 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
         x[i] = hash_unit((uint32_t)i, (uint32_t)j);
     }
     __syncthreads();
+    double *rdd = sm + 5 * n;
     if (lane == 0) {
-        // LU with partial pivoting of the tridiagonal T - lam I
+        // LU with partial pivoting of the tridiagonal T - lam I; the running
+        // diagonal and superdiagonal entries are carried in registers
+        double ddi = dd[0], dui = du[0];
         for (int i = 0; i + 1 < n; ++i) {
-            const double a = dd[i], b = dl[i];
-            if (fabs(a) >= fabs(b)) {
+            const double b = dl[i];
+            const double ddn = dd[i + 1];
+            const double dun = i + 2 < n ? du[i + 1] : 0.0;
+            if (fabs(ddi) >= fabs(b)) {
                 ipiv[i] = i;
-                const double piv = a != 0.0 ? a : tiny;
+                const double piv = ddi != 0.0 ? ddi : tiny;
                 dd[i] = piv;
                 const double f = b / piv;
                 dl[i] = f;
-                dd[i + 1] -= f * du[i];
+                du[i] = dui;
+                ddi = ddn - f * dui;
+                dui = dun;
             } else {
                 ipiv[i] = i + 1;
-                const double f = a / b;
+                const double f = ddi / b;
                 dd[i] = b;
                 dl[i] = f;
-                const double tmp = du[i];
-                du[i] = dd[i + 1];
-                dd[i + 1] = tmp - f * dd[i + 1];
-                if (i + 2 < n) {
-                    du2[i] = du[i + 1];
-                    du[i + 1] = -f * du[i + 1];
-                }
+                du[i] = ddn;
+                ddi = dui - f * ddn;
+                if (i + 2 < n) du2[i] = dun;
+                dui = -f * dun;
             }
         }
-        if (dd[n - 1] == 0.0) dd[n - 1] = tiny;
+        dd[n - 1] = ddi != 0.0 ? ddi : tiny;
     }
+    __syncthreads();
+    for (int i = lane; i < n; i += kWave) rdd[i] = 1.0 / dd[i];
     __syncthreads();
     for (int it = 0; it < 3; ++it) {
         if (lane == 0) {
+            // forward elimination with the row interchanges (x[i] carried in a register)
+            double xi = x[0];
             for (int i = 0; i + 1 < n; ++i) {
                 const double f = dl[i];
+                const double xn = x[i + 1];
                 if (ipiv[i] == i) {
-                    x[i + 1] -= f * x[i];
+                    x[i] = xi;
+                    xi = xn - f * xi;
                 } else {
-                    const double t0 = x[i];
-                    x[i] = x[i + 1];
-                    x[i + 1] = t0 - f * x[i];
+                    x[i] = xn;
+                    xi = xi - f * xn;
                 }
             }
-            x[n - 1] /= dd[n - 1];
-            x[n - 2] = (x[n - 2] - du[n - 2] * x[n - 1]) / dd[n - 2];
-            for (int i = n - 3; i >= 0; --i) x[i] = (x[i] - du[i] * x[i + 1] - du2[i] * x[i + 2]) / dd[i];
+            x[n - 1] = xi;
+            // back substitution with U (diagonal dd, superdiagonals du, du2)
+            double xb = x[n - 1] * rdd[n - 1];
+            x[n - 1] = xb;
+            double xa = (x[n - 2] - du[n - 2] * xb) * rdd[n - 2];
+            x[n - 2] = xa;
+            for (int i = n - 3; i >= 0; --i) {
+                const double xv = (x[i] - du[i] * xa - du2[i] * xb) * rdd[i];
+                x[i] = xv;
+                xb = xa;
+                xa = xv;
+            }
         }
         __syncthreads();
         double mx = 0.0;
@@ -556,18 +579,22 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
     EigWs s = eig_layout(a, n);
-    if (n > kLdsMaxN && n <= kRegMaxN) {
-        hipLaunchKernelGGL(k_tridiag_reg<kRegMaxN / 16>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e,
-                           s.tau);
-    } else if (n <= kLdsMaxN)
-        hipLaunchKernelGGL(k_tridiag_lds, dim3(1), dim3(512), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
-    else
+    if (n <= kRegMaxN) {
+        const int T = 2 * (int)ceil_div(n, 32);
+        switch (T) {
+            case 2: hipLaunchKernelGGL(k_tridiag_reg<2>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
+            case 4: hipLaunchKernelGGL(k_tridiag_reg<4>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
+            case 6: hipLaunchKernelGGL(k_tridiag_reg<6>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
+            case 8: hipLaunchKernelGGL(k_tridiag_reg<8>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
+            default: hipLaunchKernelGGL(k_tridiag_reg<10>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
+        }
+    } else
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(512), 0, st, H, ldh, n, s.A, s.Vh, s.d, s.e, s.tau);
     CD_LAUNCH_CHECK();
     const unsigned g64 = (unsigned)ceil_div(n, 64);
     hipLaunchKernelGGL(k_bisect, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, s.d, s.e, n, s.w, s.par);
     CD_LAUNCH_CHECK();
-    const size_t inv_lds = sizeof(double) * 5 * n + sizeof(int) * n;
+    const size_t inv_lds = sizeof(double) * 6 * n + sizeof(int) * n;
     hipLaunchKernelGGL(k_inviter, dim3(n), dim3(64), inv_lds, st, s.d, s.e, n, s.w, s.par, s.Zv);
     CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cluster_mgs, dim3(n), dim3(256), 0, st, s.w, s.par, n, s.Zv);

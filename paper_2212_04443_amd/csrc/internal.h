@@ -185,6 +185,10 @@ chebdav_status subspace_loss(const float *X, int64_t ldx, const double *U, int64
                              double *loss_host, float *dX, int64_t lddx, void *ws, size_t ws_bytes, hipStream_t st);
 chebdav_status adam_step(float *w, const float *g, float *m, float *v, int64_t count, double lr, double b1,
                          double b2, double eps, int step, hipStream_t st);
+chebdav_status lanczos_ws_bytes(int64_t n, int steps, size_t *bytes);
+chebdav_status lanczos_bounds(const Graph *g, int steps, uint64_t seed, double *lower, double *upper,
+                              double *alpha_out, double *beta_out, int *steps_done, void *ws, size_t ws_bytes,
+                              hipStream_t st);
 chebdav_status cluster_ws_bytes(int64_t n, int k, int K, size_t *bytes);
 chebdav_status cluster(const double *U, int64_t ldu, int64_t n, int k, int K, int max_iter, uint64_t seed,
                        int32_t *labels, double *centres, int *rounds, double *inertia, void *ws, size_t ws_bytes,

@@ -7,7 +7,10 @@ namespace {
 
 constexpr int kMaxKb = 64;
 
-// Cholesky factor and inverse for Cholesky QR.
+// Cholesky factor and inverse for Cholesky QR.  One workgroup of 256 threads on
+// a 16 x 16 grid; thread (ti, tj) owns the entries (ti + 16 a, tj + 16 b) of the
+// kb x kb working matrix in LDS, so every step updates all entries in parallel
+// without index arithmetic.
 //   scaled = 1: x_j = sqrt(G_jj) is column j's norm after projection; it is
 //     dependent if x_j < 1e-10 * norm0_j (or not finite/positive).  The
 //     remaining columns are scaled to unit norm (Gt = S G S, S = diag(1/x)) and
@@ -18,70 +21,100 @@ constexpr int kMaxKb = 64;
 // dep[j] (j < kb) = 1 for dependent columns, dep[kb] = 1 if any, dep[kb+1] = 1 if
 // the smallest diagonal entry of the (scaled) factor is below 0.01, i.e. R^{-1}
 // may amplify the block's residual components along the basis by more than 100.
+// R^{-1} comes from Gauss-Jordan elimination on [R | I] from the last row up.
 __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G, int kb,
                                                    const double *__restrict__ norm0,
                                                    double *__restrict__ Rinv, int *__restrict__ dep,
                                                    int scaled) {
+    constexpr int P = 16, TT = kMaxKb / P;
+    // R in the upper triangle of A; B = R^{-1} (upper) kept transposed in the
+    // strict lower triangle of A, its diagonal in bd
     __shared__ double A[kMaxKb][kMaxKb + 1];
+    __shared__ double bd[kMaxKb];
     __shared__ double s[kMaxKb];
     __shared__ int d[kMaxKb + 2];
-    const int tid = threadIdx.x;
-    if (tid <= kb + 1) d[tid] = 0;
-    __syncthreads();
+    const int tid = threadIdx.x, ti = tid / P, tj = tid % P;
     if (tid < kb) {
+        d[tid] = 0;
+        bd[tid] = 1.0;
         if (scaled) {
             const double x = sqrt(G[tid * kb + tid]);
             const bool bad = !(x > 0.0) || !isfinite(x) || !(x >= 1e-10 * norm0[tid]);
             s[tid] = bad ? 0.0 : 1.0 / x;
-            if (bad) d[tid] = 1;
+            d[tid] = bad;
         } else {
             s[tid] = 1.0;
         }
     }
     __syncthreads();
-    for (int e = tid; e < kb * kb; e += blockDim.x) {
-        const int i = e / kb, j = e % kb;
-        double v = G[e] * s[i] * s[j];
-        if (scaled && (d[i] || d[j])) v = (i == j) ? 1.0 : 0.0;  // placeholder, result discarded
-        A[i][j] = v;
-    }
-    __syncthreads();
-    // right-looking Cholesky, upper factor in the upper triangle of A
-    for (int k = 0; k < kb; ++k) {
-        __shared__ double piv;
-        if (tid == 0) {
-            double pv = A[k][k];
-            const double thr = scaled ? 1e-13 : 0.0;
-            if (!(pv > thr) || !isfinite(pv)) {
-                if (!d[k]) d[k] = 1;
-                pv = 1.0;
+#pragma unroll
+    for (int a = 0; a < TT; ++a)
+#pragma unroll
+        for (int b = 0; b < TT; ++b) {
+            const int i = ti + P * a, j = tj + P * b;
+            if (i < kb && j < kb && j >= i) {
+                double v = G[i * kb + j] * s[i] * s[j];
+                if (scaled && (d[i] || d[j])) v = (i == j) ? 1.0 : 0.0;  // placeholder, result discarded
+                A[i][j] = v;
             }
-            piv = sqrt(pv);
+        }
+    __syncthreads();
+    // right-looking Cholesky, upper factor
+    const double thr = scaled ? 1e-13 : 0.0;
+    for (int k = 0; k < kb; ++k) {
+        double pv = A[k][k];
+        const bool badp = !(pv > thr) || !isfinite(pv);
+        if (badp) pv = 1.0;
+        const double piv = sqrt(pv);
+        __syncthreads();
+        if (tid == 0) {
+            if (badp) d[k] = 1;
             A[k][k] = piv;
         }
+        if (tid > k && tid < kb) A[k][tid] /= piv;
         __syncthreads();
-        for (int j = k + 1 + tid; j < kb; j += blockDim.x) A[k][j] /= piv;
-        __syncthreads();
-        for (int e = tid; e < (kb - k - 1) * (kb - k - 1); e += blockDim.x) {
-            const int i = k + 1 + e / (kb - k - 1), j = k + 1 + e % (kb - k - 1);
-            if (j >= i) A[i][j] -= A[k][i] * A[k][j];
-        }
+#pragma unroll
+        for (int a = 0; a < TT; ++a)
+#pragma unroll
+            for (int b = 0; b < TT; ++b) {
+                const int i = ti + P * a, j = tj + P * b;
+                if (i > k && j >= i && j < kb) A[i][j] -= A[k][i] * A[k][j];
+            }
         __syncthreads();
     }
-    // inverse of the upper triangular factor, one column per thread (in LDS)
-    __shared__ double Ri[kMaxKb][kMaxKb + 1];
-    if (tid < kb) {
-        const int j = tid;
-        for (int i = 0; i < kb; ++i) Ri[i][j] = 0.0;
-        Ri[j][j] = 1.0 / A[j][j];
-        for (int i = j - 1; i >= 0; --i) {
-            double t = 0.0;
-            for (int l = i + 1; l <= j; ++l) t += A[i][l] * Ri[l][j];
-            Ri[i][j] = -t / A[i][i];
+    // B = I below the diagonal: zero the strict lower triangle
+#pragma unroll
+    for (int a = 0; a < TT; ++a)
+#pragma unroll
+        for (int b = 0; b < TT; ++b) {
+            const int i = ti + P * a, j = tj + P * b;
+            if (j < i && i < kb) A[i][j] = 0.0;
         }
-        for (int i = 0; i < kb; ++i) Rinv[i * kb + j] = s[i] * Ri[i][j];
-    }
     __syncthreads();
+    // Gauss-Jordan on [R | B] from the last row up: B(k, :) /= R_kk, then
+    // B(i, :) -= R_ik B(k, :) for i < k; B ends as R^{-1}
+    for (int k = kb - 1; k >= 0; --k) {
+        const double rk = 1.0 / A[k][k];
+        __syncthreads();
+        if (tid == k) bd[k] *= rk;
+        if (tid > k && tid < kb) A[tid][k] *= rk;
+        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < TT; ++a)
+#pragma unroll
+            for (int b = 0; b < TT; ++b) {
+                const int i = ti + P * a, j = tj + P * b;
+                if (i < k && j >= k && j < kb) A[j][i] -= A[i][k] * (j == k ? bd[k] : A[j][k]);
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TT; ++a)
+#pragma unroll
+        for (int b = 0; b < TT; ++b) {
+            const int i = ti + P * a, j = tj + P * b;
+            if (i < kb && j < kb) Rinv[i * kb + j] = s[i] * (i < j ? A[j][i] : i == j ? bd[i] : 0.0);
+        }
     if (tid == 0) {
         int any = 0;
         double rmin = 1.0;
@@ -89,11 +122,10 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
             any |= d[j];
             if (!d[j]) rmin = fmin(rmin, A[j][j]);
         }
-        d[kb] = any;
-        d[kb + 1] = rmin < 0.01;
+        dep[kb] = any;
+        dep[kb + 1] = rmin < 0.01;
     }
-    __syncthreads();
-    if (tid <= kb + 1) dep[tid] = d[tid];
+    if (tid < kb) dep[tid] = d[tid];
 }
 
 __global__ void k_h_insert(double *__restrict__ H, int64_t ldh, const double *__restrict__ C, int k,
