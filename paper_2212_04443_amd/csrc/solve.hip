@@ -97,13 +97,20 @@ Layout layout(Arena &a, int64_t n, const Resolved &r) {
     L.Y = a.take<double>((size_t)r.act_max * r.act_max);
     for (int i = 0; i < 2; ++i) L.Q[i] = a.take<double>((size_t)r.act_max * r.act_max);
     L.ones = a.take<double>(r.act_max);
-    L.D = a.take<double>(r.act_max);
-    L.res = a.take<double>(std::max(r.act_max, r.lmax));
-    L.hd = a.take<double>(r.act_max);
+    // Ritz values and residual norms side by side (one device-to-host copy)
+    L.D = a.take<double>((size_t)r.act_max + std::max(r.act_max, r.lmax));
+    L.res = L.D + r.act_max;
     L.ev = a.take<double>(r.lmax);
     size_t pe = std::max(gram_partial_elems(n, r.act_max, r.kb), colnorm_partial_elems(n, std::min(256, std::max(r.act_max, r.kb))));
     L.part = a.take<double>(pe);
-    L.map = a.take<int32_t>((size_t)2 * r.act_max + 2 * r.lmax);
+    // index maps followed by the new diagonal of H, laid out as in the pinned
+    // host buffer (one host-to-device copy per iteration)
+    {
+        const size_t nm = (size_t)2 * r.act_max + 2 * r.lmax;
+        char *mh = a.take<char>(sizeof(int32_t) * nm + sizeof(double) * (r.act_max + r.lmax));
+        L.map = reinterpret_cast<int32_t *>(mh);
+        L.hd = reinterpret_cast<double *>(mh + sizeof(int32_t) * nm);
+    }
     L.filt_b = std::max(filter_ws_bytes(n, r.kb, CHEBDAV_F64),
                         r.fdt == CHEBDAV_F32 ? filter_ws_bytes(n, r.kb, CHEBDAV_F32) : 0);
     L.filt = a.take<char>(L.filt_b);
@@ -307,8 +314,7 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             ldp = kb;
         }
         CD_TRY(colnorms(PW, ldp, PV, ldp, L.D, nres, n, L.res, L.part, st));
-        CD_HIP(hipMemcpyAsync(h_vals, L.D, sizeof(double) * kact, hipMemcpyDeviceToHost, st));
-        CD_HIP(hipMemcpyAsync(h_vals + am, L.res, sizeof(double) * nres, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipMemcpyAsync(h_vals, L.D, sizeof(double) * (am + nres), hipMemcpyDeviceToHost, st));
         CD_HIP(hipStreamSynchronize(st));
         for (int i = 0; i < kact; ++i) D[i] = h_vals[i];
         for (int i = 0; i < nres; ++i) res[i] = h_vals[am + i];
@@ -323,11 +329,24 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         double min_open_res = INFINITY;
         for (int i = 0; i < nres; ++i)
             if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
+        // host decisions first (steps 12-16), then one upload of the maps and the new diagonal
+        const bool done = kc + ec >= r.k_want;
+        int kact_next = kact - ec;
+        bool outer = false;
+        if (!done && kc + ec + kact_next + kb > r.dim_max) {
+            kact_next = r.dim_max - 2 * kb - (kc + ec);
+            outer = true;
+        }
         int32_t *m_conv = h_map, *m_rest = h_map + am;
+        for (int t = 0; t < ec; ++t) m_conv[t] = conv[t];
+        for (int t = 0; t < (int)rest.size(); ++t) m_rest[t] = rest[t];
+        std::vector<double> Dact(rest.size());
+        for (size_t t = 0; t < rest.size(); ++t) Dact[t] = D[rest[t]];
+        if (!done)
+            for (int t = 0; t < kact_next; ++t) h_diag[t] = Dact[t];
+        const size_t up_bytes = reinterpret_cast<char *>(h_diag + (done ? 0 : kact_next)) - reinterpret_cast<char *>(h_map);
+        if (ec || !done) CD_HIP(hipMemcpyAsync(L.map, h_map, up_bytes, hipMemcpyHostToDevice, st));
         if (ec) {
-            for (int t = 0; t < ec; ++t) m_conv[t] = conv[t];
-            for (int t = 0; t < (int)rest.size(); ++t) m_rest[t] = rest[t];
-            CD_HIP(hipMemcpyAsync(L.map, h_map, sizeof(int32_t) * 2 * am, hipMemcpyHostToDevice, st));
             // lock: append the converged Ritz vectors to Vl
             CD_TRY(gather_cols(PV, ldp, L.Vl + kc, r.lmax, L.map, ec, n, st));
             for (int t = 0; t < ec; ++t) locked.push_back(D[conv[t]]);
@@ -337,25 +356,19 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             kact -= ec;
         }
         // step 13
-        if (kc >= r.k_want) {
+        if (done) {
             result = CHEBDAV_OK;
             break;
         }
-        std::vector<double> Dact(kact);
-        for (int t = 0; t < kact; ++t) Dact[t] = D[rest[t]];
         // step 16: outer restart (ksub = kc + kact); B also rotated when it is full
-        if (kc + kact + kb > r.dim_max) {
-            kact = r.dim_max - 2 * kb - kc;
+        if (outer) {
+            kact = kact_next;
             CD_TRY(compress(kact));
         } else if (kr + kb > am) {
             CD_TRY(compress(kact));
         }
         // step 15: H = diag of the retained non-converged Ritz values
-        for (int t = 0; t < kact; ++t) h_diag[t] = Dact[t];
-        if (kact) {
-            CD_HIP(hipMemcpyAsync(L.hd, h_diag, sizeof(double) * kact, hipMemcpyHostToDevice, st));
-            CD_TRY(h_set_diag(L.H, am, L.hd, kact, st));
-        }
+        if (kact) CD_TRY(h_set_diag(L.H, am, L.hd, kact, st));
         // step 17: next block = [unused V_init columns, leading Ritz vectors, random]
         {
             const int n_init = std::max(0, std::min(ec, k_init - ki));
