@@ -84,10 +84,15 @@ chebdav_status dinv_table(const int32_t *deg, double *dinv, int64_t n, hipStream
 
 // ---- spmm.hip: Y = alpha * dinv .* (S (dinv .* U)) + beta U + gamma Z
 // T = element type of U and Z (and the arithmetic), TO = element type of Y.
+// Flags of the fused sparse step.  kStepScaled: U and Z hold s .* U (s = dinv,
+// 1 on isolated rows), the neighbour rows are summed unscaled and the row sum
+// takes dinv_i^2.  kStepOutMulS / kStepOutDivS: output times / divided by s_i.
+// kStepZMulS: Z is unscaled and is multiplied by s_i.
+constexpr int kStepOutMulS = 1, kStepOutDivS = 2, kStepZMulS = 4, kStepScaled = 8;
 template <typename T, typename TO>
 chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, double gamma,
                                 const T *U, int64_t ldu, const T *Z, int64_t ldz, TO *Y,
-                                int64_t ldy, int w, hipStream_t st);
+                                int64_t ldy, int w, hipStream_t st, int flags = 0);
 
 // Filter driver (Alg. 3); workspace laid out by filter_layout.
 size_t filter_ws_bytes(int64_t n, int kb, chebdav_dtype dt);

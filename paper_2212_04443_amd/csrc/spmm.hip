@@ -14,6 +14,9 @@
 // contiguous range of rows (the gathered rows of block-structured graphs then
 // stay in that XCD's L2); the ranges are balanced by nonzeros, so graphs whose
 // degrees vary along the node order (power laws, hubs first) keep every XCD busy.
+// Inside the filter the work blocks are kept scaled by s = dinv (1 on isolated
+// rows), so all steps after the first gather neighbour rows without their dinv
+// (one gathered stream per neighbour instead of two).
 #include <algorithm>
 
 #include "device_util.h"
@@ -63,12 +66,16 @@ struct Chunk {
     static constexpr int UNR = CH < 8 ? CH : 8;
 };
 
-template <typename T, typename TO, int VE, int G>
+// NBR = true: the neighbour rows are scaled by their dinv (the plain product);
+// NBR = false: the block is already scaled by s = dinv (1 on isolated rows), so
+// the neighbour rows are summed as they are and the row sum takes dinv_i^2.
+// flags (kStep*): the output times s_i or divided by s_i, Z times s_i.
+template <typename T, typename TO, int VE, int G, bool NBR>
 __global__ void __launch_bounds__(kBlock)
     k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                 const T *__restrict__ dinv, T alpha, T beta, T gamma, const T *__restrict__ U,
                 int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
-                int w, XcdRanges xr) {
+                int w, XcdRanges xr, int flags) {
     constexpr int GPB = kBlock / G;  // rows per block
     constexpr int CH = Chunk<G>::CH, PER = Chunk<G>::PER, UNR = Chunk<G>::UNR;
     const int lane = lane_id();
@@ -108,7 +115,7 @@ __global__ void __launch_bounds__(kBlock)
         for (int k = 0; k < PER; ++k) {
             const int64_t nidx = base + CH + gl + (int64_t)k * G;
             jn[k] = nidx < end ? col[nidx] : 0;
-            dl[k] = (base + gl + (int64_t)k * G) < end ? dinv[jl[k]] : T(0);
+            if constexpr (NBR) dl[k] = (base + gl + (int64_t)k * G) < end ? dinv[jl[k]] : T(0);
         }
         for (int t0 = 0; t0 < cnt; t0 += UNR) {
             T u[UNR][VE];
@@ -125,10 +132,15 @@ __global__ void __launch_bounds__(kBlock)
             }
 #pragma unroll
             for (int i = 0; i < UNR; ++i) {
-                const int t = t0 + i;
-                const T dj = __shfl(dl[(t / G) % PER], t % G, G);
+                if constexpr (NBR) {
+                    const int t = t0 + i;
+                    const T dj = __shfl(dl[(t / G) % PER], t % G, G);
 #pragma unroll
-                for (int e = 0; e < VE; ++e) acc[e] += dj * u[i][e];
+                    for (int e = 0; e < VE; ++e) acc[e] += dj * u[i][e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VE; ++e) acc[e] += u[i][e];
+                }
             }
         }
 #pragma unroll
@@ -136,23 +148,31 @@ __global__ void __launch_bounds__(kBlock)
     }
     if (!active) return;
     TO *yp = Y + r * ldy + c0;
-    if constexpr (sizeof(TO) == sizeof(T)) {
-        T y[VE];
+    const T si = di > T(0) ? di : T(1);
+    const T a_i = NBR ? alpha * di : alpha * (di * di);
+    const T g_i = (flags & kStepZMulS) ? gamma * si : gamma;
+    T y[VE];
 #pragma unroll
-        for (int e = 0; e < VE; ++e) y[e] = alpha * (di * acc[e]) + beta * ur[e] + gamma * zr[e];
+    for (int e = 0; e < VE; ++e) {
+        T v = a_i * acc[e] + beta * ur[e] + g_i * zr[e];
+        if (flags & kStepOutMulS) v *= si;
+        if (flags & kStepOutDivS) v /= si;
+        y[e] = v;
+    }
+    if constexpr (sizeof(TO) == sizeof(T)) {
         using VT = typename VecT<T, VE>::type;
         VT v;
         __builtin_memcpy(&v, y, sizeof(VT));
         *reinterpret_cast<VT *>(yp) = v;
     } else {
 #pragma unroll
-        for (int e = 0; e < VE; ++e) yp[e] = (TO)(alpha * (di * acc[e]) + beta * ur[e] + gamma * zr[e]);
+        for (int e = 0; e < VE; ++e) yp[e] = (TO)y[e];
     }
 }
 
-template <typename T, typename TO, int VE>
+template <typename T, typename TO, int VE, bool NBR>
 chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *U, int64_t ldu,
-                         const T *Z, int64_t ldz, TO *Y, int64_t ldy, int w, hipStream_t st) {
+                         const T *Z, int64_t ldz, TO *Y, int64_t ldy, int w, int flags, hipStream_t st) {
     int lanes = (w + VE - 1) / VE;
     int G = 1;
     while (G < lanes) G <<= 1;
@@ -166,8 +186,8 @@ chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *
     const dim3 gr((unsigned)grid), bl(kBlock);
 #define CD_CASE(GG)                                                                                 \
     case GG:                                                                                        \
-        hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG>), gr, bl, 0, st, g->n, g->row_ptr, g->col,   \
-                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr);                           \
+        hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG, NBR>), gr, bl, 0, st, g->n, g->row_ptr, g->col, \
+                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr, flags);                    \
         break;
     switch (G) {
         CD_CASE(1)
@@ -192,7 +212,7 @@ inline bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_
 template <typename T, typename TO>
 chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, double gamma,
                                 const T *U, int64_t ldu, const T *Z, int64_t ldz, TO *Y,
-                                int64_t ldy, int w, hipStream_t st) {
+                                int64_t ldy, int w, hipStream_t st, int flags) {
     if (w < 1) return fail(CHEBDAV_EINVAL, "block width must be >= 1");
     if (ldu < w || ldy < w || (Z && ldz < w)) return fail(CHEBDAV_EINVAL, "leading dimension < width");
     if (!U || !Y) return fail(CHEBDAV_EINVAL, "NULL block");
@@ -211,13 +231,21 @@ chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, doubl
                          (!Zp || ldz % V == 0) && aligned(U + c0, 16) && aligned(Y + c0, 16) &&
                          (!Zp || aligned(Zp + c0, 16));
         const T *Zc = Zp ? Zp + c0 : nullptr;
+        const bool scaled = (flags & kStepScaled) != 0;
         if (vec) {
-            CD_TRY((launch_ve<T, TO, V>(g, dinv, a, b, c, U + c0, ldu, Zc, ldz, Y + c0, ldy, pw, st)));
+            if (scaled)
+                CD_TRY((launch_ve<T, TO, V, false>(g, dinv, a, b, c, U + c0, ldu, Zc, ldz, Y + c0, ldy, pw, flags, st)));
+            else
+                CD_TRY((launch_ve<T, TO, V, true>(g, dinv, a, b, c, U + c0, ldu, Zc, ldz, Y + c0, ldy, pw, flags, st)));
         } else {
             for (int s = 0; s < pw; s += 64) {
                 const int sw = std::min(64, pw - s);
-                CD_TRY((launch_ve<T, TO, 1>(g, dinv, a, b, c, U + c0 + s, ldu, Zp ? Zc + s : nullptr, ldz,
-                                            Y + c0 + s, ldy, sw, st)));
+                if (scaled)
+                    CD_TRY((launch_ve<T, TO, 1, false>(g, dinv, a, b, c, U + c0 + s, ldu, Zp ? Zc + s : nullptr, ldz,
+                                                       Y + c0 + s, ldy, sw, flags, st)));
+                else
+                    CD_TRY((launch_ve<T, TO, 1, true>(g, dinv, a, b, c, U + c0 + s, ldu, Zp ? Zc + s : nullptr, ldz,
+                                                      Y + c0 + s, ldy, sw, flags, st)));
             }
         }
     }
@@ -226,13 +254,13 @@ chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, doubl
 
 template chebdav_status launch_cheb_step<double, double>(const Graph *, double, double, double,
                                                          const double *, int64_t, const double *,
-                                                         int64_t, double *, int64_t, int, hipStream_t);
+                                                         int64_t, double *, int64_t, int, hipStream_t, int);
 template chebdav_status launch_cheb_step<float, float>(const Graph *, double, double, double,
                                                        const float *, int64_t, const float *,
-                                                       int64_t, float *, int64_t, int, hipStream_t);
+                                                       int64_t, float *, int64_t, int, hipStream_t, int);
 template chebdav_status launch_cheb_step<float, double>(const Graph *, double, double, double,
                                                         const float *, int64_t, const float *,
-                                                        int64_t, double *, int64_t, int, hipStream_t);
+                                                        int64_t, double *, int64_t, int, hipStream_t, int);
 
 // ---------------------------------------------------------------------------
 // Filter driver (Alg. 3).  With c = (cut+upper)/2, e = (upper-cut)/2,
@@ -261,12 +289,16 @@ chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y,
     double sigma = e / (scale_pt - c);
     const double tau = 2.0 / sigma;
     const int64_t ldb = kb;
+    // The work blocks hold s .* U_k (s = dinv, 1 on isolated rows): A = I - diag(s)
+    // S diag(s), so s .* (A U) = s .* U - s^2 .* (S (s .* U)) and the steps after the
+    // first gather unscaled rows (no per-neighbour dinv).  The first step scales
+    // its output, the second scales its Z = X, the last divides its output by s.
     // step 1
     {
         const double al = -sigma / e, be = sigma * (1.0 - c) / e;
         if (m == 1)
             return launch_cheb_step<T, double>(g, al, be, 0.0, x0, ldx0, nullptr, 0, Y, ldy, kb, st);
-        CD_TRY((launch_cheb_step<T, T>(g, al, be, 0.0, x0, ldx0, nullptr, 0, bufs[0], ldb, kb, st)));
+        CD_TRY((launch_cheb_step<T, T>(g, al, be, 0.0, x0, ldx0, nullptr, 0, bufs[0], ldb, kb, st, kStepOutMulS)));
     }
     const T *prev = x0;
     int64_t ldp = ldx0;
@@ -276,11 +308,12 @@ chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y,
         const double al = -2.0 * sigma1 / e;
         const double be = 2.0 * sigma1 * (1.0 - c) / e;
         const double ga = -sigma * sigma1;
+        const int fl = kStepScaled | (k == 2 ? kStepZMulS : 0);
         if (k == m) {
-            CD_TRY((launch_cheb_step<T, double>(g, al, be, ga, cur, ldb, prev, ldp, Y, ldy, kb, st)));
+            CD_TRY((launch_cheb_step<T, double>(g, al, be, ga, cur, ldb, prev, ldp, Y, ldy, kb, st, fl | kStepOutDivS)));
         } else {
             T *out = bufs[(k - 1) % 3];
-            CD_TRY((launch_cheb_step<T, T>(g, al, be, ga, cur, ldb, prev, ldp, out, ldb, kb, st)));
+            CD_TRY((launch_cheb_step<T, T>(g, al, be, ga, cur, ldb, prev, ldp, out, ldb, kb, st, fl)));
             prev = cur;
             ldp = ldb;
             cur = out;
