@@ -143,20 +143,29 @@ __global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, i
     tridiag_run(Ag, H, ldh, n, Vh, d, e, tau, v, wsh, red);
 }
 
-// Register-resident variant for n <= 16 T: the working matrix is spread over a
-// 16 x 16 thread grid, thread (pc, pr) = (tid / 16, tid % 16) holding
-// A(pr + 16 a, pc + 16 b) for a, b < T, so a row group of 16 lanes (one pc) owns
+// Sum over a group of P consecutive lanes (P = 16: DPP row rotations; P = 32:
+// plus one exchange between the two 16-lane rows), the same value in every lane.
+template <int P>
+__device__ inline double group_sum(double v) {
+    v = row16_sum(v);
+    if constexpr (P == 32) v += __shfl_xor(v, 16, kWave);
+    return v;
+}
+
+// Register-resident variant for n <= P T: the working matrix is spread over a
+// P x P thread grid (P = 32: 1024 threads), thread (pc, pr) = (tid / P, tid % P)
+// holding A(pr + P a, pc + P b) for a, b < T, so a group of P lanes (one pc) owns
 // whole columns.  A step k then needs two barriers: the row group that owns
 // column k forms the reflector from its registers (sums over its 16 lanes by
 // DPP row rotations) and publishes v; every thread forms its column sums of
 // A v (row rotations again; A is symmetric, so column sums are p), the row
 // groups publish p and their share of p^T v; every thread then updates its
 // entries.  Tiles whose rows or columns are all finished are skipped.
-template <int T>
-__global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ H, int64_t ldh, int n,
-                                                     double *__restrict__ Vh, double *__restrict__ d,
-                                                     double *__restrict__ e, double *__restrict__ tau) {
-    constexpr int P = 16, NV = P * T;
+template <int P, int T>
+__global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict__ H, int64_t ldh, int n,
+                                                       double *__restrict__ Vh, double *__restrict__ d,
+                                                       double *__restrict__ e, double *__restrict__ tau) {
+    constexpr int NV = P * T;
     __shared__ double vs[NV], ps[NV], kp[P], scal[2];
     const int tid = threadIdx.x, pc = tid / P, pr = tid % P;
     double A[T][T];
@@ -187,9 +196,9 @@ __global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ 
                 if (i == k + 1) x0 = col[a];
                 if (i == k) dk = col[a];
             }
-            const double ss = row16_sum(part);
-            x0 = row16_sum(x0);  // one lane holds it, the others add zeros
-            dk = row16_sum(dk);
+            const double ss = group_sum<P>(part);
+            x0 = group_sum<P>(x0);  // one lane holds it, the others add zeros
+            dk = group_sum<P>(dk);
             double t = 0.0, v0 = 0.0, alpha = x0;
             if (ss != 0.0) {
                 alpha = -copysign(sqrt(x0 * x0 + ss), x0);
@@ -232,7 +241,7 @@ __global__ void __launch_bounds__(256) k_tridiag_reg(const double *__restrict__ 
 #pragma unroll
             for (int a = 0; a < T; ++a)
                 if (P * (a + 1) - 1 > k) sacc += A[a][b] * vr[a];
-            q[b] = t * row16_sum(sacc);
+            q[b] = t * group_sum<P>(sacc);
             kpart += q[b] * vc[b];
         }
 #pragma unroll
@@ -403,14 +412,14 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
                 ipiv[i] = i;
                 const double piv = ddi != 0.0 ? ddi : tiny;
                 dd[i] = piv;
-                const double f = b / piv;
+                const double f = b * recip(piv);
                 dl[i] = f;
                 du[i] = dui;
                 ddi = ddn - f * dui;
                 dui = dun;
             } else {
                 ipiv[i] = i + 1;
-                const double f = ddi / b;
+                const double f = ddi * recip(b);
                 dd[i] = b;
                 dl[i] = f;
                 du[i] = ddn;
@@ -502,7 +511,7 @@ __global__ void __launch_bounds__(256) k_cluster_mgs(const double *__restrict__ 
 }
 
 // Y(:, j) = Q z_j with Q = H_0 H_1 ... H_{n-3}; one wavefront per eigenvector.
-constexpr int kTpl = kMaxN / kWave;
+template <int kTpl>
 __global__ void __launch_bounds__(256) k_backtransform(const double *__restrict__ Vh,
                                                        const double *__restrict__ tau,
                                                        const double *__restrict__ Zv, int n,
@@ -510,7 +519,7 @@ __global__ void __launch_bounds__(256) k_backtransform(const double *__restrict_
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
     const int lane = lane_id();
-    const int tpl = (n + kWave - 1) / kWave;
+    constexpr int tpl = kTpl;  // n <= 64 kTpl
     double z[kTpl];
 #pragma unroll
     for (int t = 0; t < kTpl; ++t) {
@@ -580,14 +589,19 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     a.cap = ws_bytes;
     EigWs s = eig_layout(a, n);
     if (n <= kRegMaxN) {
-        const int T = 2 * (int)ceil_div(n, 32);
-        switch (T) {
-            case 2: hipLaunchKernelGGL(k_tridiag_reg<2>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
-            case 4: hipLaunchKernelGGL(k_tridiag_reg<4>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
-            case 6: hipLaunchKernelGGL(k_tridiag_reg<6>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
-            case 8: hipLaunchKernelGGL(k_tridiag_reg<8>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
-            default: hipLaunchKernelGGL(k_tridiag_reg<10>, dim3(1), dim3(256), 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau); break;
-        }
+        // 16 x 16 grid up to n = 64 and above 128 (a 32 x 32 grid would spill
+        // there), 32 x 32 grid for 64 < n <= 128 (measured faster)
+        const dim3 b256(256), b1024(1024);
+        if (n <= 32)
+            hipLaunchKernelGGL((k_tridiag_reg<16, 2>), dim3(1), b256, 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
+        else if (n <= 64)
+            hipLaunchKernelGGL((k_tridiag_reg<16, 4>), dim3(1), b256, 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
+        else if (n <= 96)
+            hipLaunchKernelGGL((k_tridiag_reg<32, 3>), dim3(1), b1024, 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
+        else if (n <= 128)
+            hipLaunchKernelGGL((k_tridiag_reg<32, 4>), dim3(1), b1024, 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
+        else
+            hipLaunchKernelGGL((k_tridiag_reg<16, 10>), dim3(1), b256, 0, st, H, ldh, n, s.Vh, s.d, s.e, s.tau);
     } else
         hipLaunchKernelGGL(k_tridiag, dim3(1), dim3(512), 0, st, H, ldh, n, s.A, s.Vh, s.d, s.e, s.tau);
     CD_LAUNCH_CHECK();
@@ -599,9 +613,21 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     CD_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_cluster_mgs, dim3(n), dim3(256), 0, st, s.w, s.par, n, s.Zv);
     CD_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_backtransform, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, st, s.Vh, s.tau,
-                       s.Zv, n, s.T, n);
-    CD_LAUNCH_CHECK();
+    {
+        const dim3 gb((unsigned)ceil_div(n, 4));
+        switch ((int)ceil_div(n, kWave)) {
+            case 1: hipLaunchKernelGGL(k_backtransform<1>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 2: hipLaunchKernelGGL(k_backtransform<2>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 3: hipLaunchKernelGGL(k_backtransform<3>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 4: hipLaunchKernelGGL(k_backtransform<4>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 5: hipLaunchKernelGGL(k_backtransform<5>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 6: hipLaunchKernelGGL(k_backtransform<6>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 7: hipLaunchKernelGGL(k_backtransform<7>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            case 8: hipLaunchKernelGGL(k_backtransform<8>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+            default: hipLaunchKernelGGL(k_backtransform<kMaxN / kWave>, gb, dim3(256), 0, st, s.Vh, s.tau, s.Zv, n, s.T, n); break;
+        }
+        CD_LAUNCH_CHECK();
+    }
     // one Newton-Schulz step Y = T (3 I - T^T T)/2: inverse-iteration vectors of
     // eigenvalues further apart than the tight-cluster threshold are orthogonal
     // to about 1e-10, so one step brings the defect to rounding level
