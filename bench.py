@@ -52,9 +52,10 @@ def flops_per_step(n, nnz, kb):
 def run_forms(cd, torch, g, cfg, forms, steps, warmup, seed):
     out = {}
     for form in forms:
-        dt = cd.F64 if form == "f64" else cd.F32
+        dt = cd.F32 if form == "f32" else cd.F64
+        orth = "tsqr" if form == "f64_tsqr" else "cholqr"
         p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed,
-                           filter_dtype=dt, timing=True)
+                           filter_dtype=dt, timing=True, orth=orth)
         ws = torch.empty(cd.solve_workspace_size(g, p), dtype=torch.uint8, device="cuda")
         for _ in range(warmup):
             cd.solve(g, p, workspace=ws)
@@ -217,7 +218,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sbm200k")
-    ap.add_argument("--forms", default="f64,f32", help="comma list of f64,f32; the first is primary")
+    ap.add_argument("--forms", default="f64,f32,f64_tsqr",
+                    help="comma list of f64, f32 (FP32 filter), f64_tsqr (Householder TSQR in place of "
+                         "Cholesky QR); the first is primary")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the GCN warm-start forms")
@@ -278,7 +281,7 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f64" if forms[0] == "f64" else "f32+f64",
+        "dtype": "f32+f64" if forms[0] == "f32" else "f64",
         "data": "synthetic",
         "config": {
             "workload": describe(args.workload, n, g.nnz, cfg),
@@ -307,6 +310,8 @@ def main():
     if len(forms) > 1:
         a, b2 = res[forms[0]]["evals"], res[forms[1]]["evals"]
         line["forms_max_dlambda"] = float(np.abs(a - b2).max())
+        for f in forms[2:]:
+            line[f + "_max_dlambda"] = float(np.abs(res[f]["evals"] - a).max())
     for fdt in ([cd.F64, cd.F32] if not args.no_warm_start else []):
         wf = warm_start_form(cd, torch, g, cfg, args.steps, args.seed, fdt)
         if wf is not None:

@@ -41,6 +41,10 @@ typedef enum {
 
 typedef enum { CHEBDAV_F64 = 0, CHEBDAV_F32 = 1 } chebdav_dtype;
 
+/* Orthonormalization of a new block after its projections (Alg. 2 step 6):
+ * Cholesky QR twice, or Householder TSQR (Sec. 5). */
+typedef enum { CHEBDAV_ORTH_CHOLQR = 0, CHEBDAV_ORTH_TSQR = 1 } chebdav_orth;
+
 /* Opaque handle owning the device CSR pattern of S and its degree scaling. */
 typedef struct chebdav_graph chebdav_graph;
 
@@ -121,19 +125,43 @@ chebdav_status chebdav_filter(const chebdav_graph *g, const double *X, int64_t l
  * columns of V (n x ksub, device double, row-major, ldv; may be NULL if
  * ksub == 0), and spans the same space as (I - V V^T) X_in when that has full
  * numerical rank.  Method: two block classical Gram-Schmidt passes against V,
- * then Cholesky QR with a dependence test, then a third pass and a second
- * Cholesky QR.  A column whose norm after projection is below 1e-10 of its
- * norm before, or whose pivot in the scaled Gram matrix is below 1e-13, is
- * numerically dependent and replaced by a Philox4x32-10 column (key = seed,
- * counters numbered from first_random_col), then everything is redone.
- * n_replaced (host, may be NULL) receives the number of replacements.
+ * then (method CHOLQR) Cholesky QR with a dependence test, then a third pass
+ * against V only when the smallest diagonal entry of the scaled Cholesky factor
+ * is below 0.01, and a second Cholesky QR; or (method TSQR) the same with
+ * Householder TSQR (chebdav_tsqr) in place of each Cholesky QR, its R deciding
+ * dependence with the same thresholds.  A column whose norm after projection
+ * is below 1e-10 of its norm before, or whose squared pivot in the
+ * column-scaled factor is below 1e-13, is numerically dependent and replaced
+ * by a Philox4x32-10 column (key = seed, counters numbered from
+ * first_random_col), then everything is redone.  n_replaced (host, may be
+ * NULL) receives the number of replacements.  1 <= kb <= 64.
  * Errors: EBREAKDOWN if dependence persists after 3 rounds of replacement.
  * ------------------------------------------------------------------------ */
-chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, size_t *bytes);
+chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, chebdav_orth method,
+                                                     size_t *bytes);
 chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, double *X,
                                       int64_t ldx, int kb, int64_t n, uint64_t seed,
-                                      uint64_t first_random_col, int *n_replaced,
+                                      uint64_t first_random_col, chebdav_orth method, int *n_replaced,
                                       void *workspace, size_t ws_bytes, void *hip_stream);
+
+/* ------------------------------------------------------------------------
+ * Tall-skinny QR (Sec. 5, distributed orthonormalization: TSQR over a tree of
+ * row blocks, here the row chunks of one GPU).  X = Q R for X (n x kb, device
+ * double, row-major, ldx >= kb; only read): Q (n x kb, device double,
+ * row-major, ldq >= kb) with orthonormal columns, R (kb x kb, device double,
+ * row-major, ldr >= kb) upper triangular with a non-negative diagonal and
+ * zeros below it; for X of full column rank this is the unique thin QR.  Q may
+ * be X itself (same ld); otherwise Q, R and X must not overlap.
+ * Method: Householder QR of row chunks of 256..2048 rows (one workgroup each),
+ * their R factors stacked and factored again up a tree of fan-in >= 4, Q formed
+ * top-down from the reflectors of every level.  Stream-ordered, no host sync.
+ * workspace: device, at least chebdav_tsqr_workspace_size() bytes.
+ * Errors: EINVAL if n < kb or a leading dimension is below kb; EUNSUPPORTED
+ * unless 1 <= kb <= 64.
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_tsqr_workspace_size(int64_t n, int kb, size_t *bytes);
+chebdav_status chebdav_tsqr(const double *X, int64_t ldx, int64_t n, int kb, double *Q, int64_t ldq,
+                            double *R, int64_t ldr, void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Solver (Alg. 2: block Chebyshev-Davidson with inner-outer restart and
@@ -157,6 +185,7 @@ typedef struct {
                                (0 -> 1e-5); every other step is always FP64               */
     uint64_t seed;          /* Philox key for all random vectors                           */
     int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
+    chebdav_orth orth;      /* orthonormalization of new blocks (default CHOLQR)           */
 } chebdav_params;
 
 typedef struct {

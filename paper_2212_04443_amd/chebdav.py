@@ -23,6 +23,8 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libchebdav
 
 OK, EINVAL, ENOMEM, EHIP, ENOCONV, EBREAKDOWN, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 F64, F32 = 0, 1
+ORTH_CHOLQR, ORTH_TSQR = 0, 1
+_ORTH = {"cholqr": ORTH_CHOLQR, "tsqr": ORTH_TSQR}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "EBREAKDOWN",
            -6: "EUNSUPPORTED"}
 
@@ -37,6 +39,7 @@ EXPORTED = [
     "chebdav_rayleigh_ritz_workspace_size", "chebdav_rayleigh_ritz",
     "chebdav_cluster_workspace_size", "chebdav_cluster",
     "chebdav_lanczos_bounds_workspace_size", "chebdav_lanczos_bounds",
+    "chebdav_tsqr_workspace_size", "chebdav_tsqr",
 ]
 
 
@@ -53,6 +56,7 @@ class Params(ctypes.Structure):
         ("k_ri", ctypes.c_int), ("upperb", ctypes.c_double), ("lowb", ctypes.c_double),
         ("low_nwb0", ctypes.c_double), ("filter_dtype", ctypes.c_int),
         ("f32_switch_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("timing", ctypes.c_int),
+        ("orth", ctypes.c_int),
     ]
 
 
@@ -83,8 +87,10 @@ def _load():
         "chebdav_spmm": [p, d, d, d, p, p, p, i64, i32, i32, p],
         "chebdav_filter_workspace_size": [p, i32, i32, P(sz)],
         "chebdav_filter": [p, p, i64, p, i64, i32, i32, d, d, d, i32, p, sz, p],
-        "chebdav_orthonormalize_workspace_size": [i64, i32, i32, P(sz)],
-        "chebdav_orthonormalize": [p, i64, i32, p, i64, i32, i64, u64, u64, P(i32), p, sz, p],
+        "chebdav_orthonormalize_workspace_size": [i64, i32, i32, i32, P(sz)],
+        "chebdav_orthonormalize": [p, i64, i32, p, i64, i32, i64, u64, u64, i32, P(i32), p, sz, p],
+        "chebdav_tsqr_workspace_size": [i64, i32, P(sz)],
+        "chebdav_tsqr": [p, i64, i64, i32, p, i64, p, i64, p, sz, p],
         "chebdav_solve_workspace_size": [p, P(Params), P(sz)],
         "chebdav_solve": [p, P(Params), p, i32, p, p, P(Stats), p, sz, p],
         "chebdav_small_eig_workspace_size": [i32, P(sz)],
@@ -237,25 +243,43 @@ def filter(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float = 2.0, sc
     return Y
 
 
-def orthonormalize(V, X: torch.Tensor, seed: int = 0, first_random_col: int = 0, stream=None) -> int:
-    """chebdav_orthonormalize, in place on X; returns the number of replaced columns."""
+def orthonormalize(V, X: torch.Tensor, seed: int = 0, first_random_col: int = 0, method: str = "cholqr",
+                   stream=None) -> int:
+    """chebdav_orthonormalize, in place on X; returns the number of replaced columns.
+    method: "cholqr" (Cholesky QR twice) or "tsqr" (Householder TSQR)."""
     n, kb = X.shape
     ksub = 0 if V is None else V.shape[1]
+    meth = _ORTH[method]
     nb = ctypes.c_size_t()
-    _check(_lib.chebdav_orthonormalize_workspace_size(n, ksub, kb, ctypes.byref(nb)))
+    _check(_lib.chebdav_orthonormalize_workspace_size(n, ksub, kb, meth, ctypes.byref(nb)))
     ws = _workspace(nb.value, X.device)
     rep = ctypes.c_int(0)
     _check(_lib.chebdav_orthonormalize(_ptr(V) if ksub else ctypes.c_void_p(0), _ld(V) if ksub else 1,
-                                       ksub, _ptr(X), _ld(X), kb, n, seed, first_random_col,
+                                       ksub, _ptr(X), _ld(X), kb, n, seed, first_random_col, meth,
                                        ctypes.byref(rep), _ptr(ws), ws.numel(), _stream(stream)))
     return rep.value
 
 
+def tsqr(X: torch.Tensor, Q: torch.Tensor | None = None, stream=None):
+    """chebdav_tsqr: X = Q R (thin QR, R with a non-negative diagonal).  Q may be X
+    itself (in place).  Returns (Q, R)."""
+    n, kb = X.shape
+    if Q is None:
+        Q = torch.empty((n, kb), dtype=torch.float64, device=X.device)
+    R = torch.empty((kb, kb), dtype=torch.float64, device=X.device)
+    nb = ctypes.c_size_t()
+    _check(_lib.chebdav_tsqr_workspace_size(n, kb, ctypes.byref(nb)))
+    ws = _workspace(nb.value, X.device)
+    _check(_lib.chebdav_tsqr(_ptr(X), _ld(X), n, kb, _ptr(Q), _ld(Q), _ptr(R), _ld(R), _ptr(ws), ws.numel(),
+                             _stream(stream)))
+    return Q, R
+
+
 def make_params(k_want, kb, m, tol=1e-8, itmax=0, act_max=0, dim_max=0, k_ri=0, upperb=2.0,
                 lowb=0.0, low_nwb0=math.nan, filter_dtype=F64, f32_switch_tol=0.0, seed=0,
-                timing=False) -> Params:
+                timing=False, orth="cholqr") -> Params:
     return Params(k_want, kb, m, itmax, tol, act_max, dim_max, k_ri, upperb, lowb, low_nwb0,
-                  filter_dtype, f32_switch_tol, seed, 1 if timing else 0)
+                  filter_dtype, f32_switch_tol, seed, 1 if timing else 0, _ORTH[orth])
 
 
 def solve_workspace_size(g: Graph, params: Params) -> int:

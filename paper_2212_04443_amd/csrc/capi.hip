@@ -149,15 +149,36 @@ chebdav_status chebdav_filter(const chebdav_graph *gh, const double *X, int64_t 
                       as_stream(hip_stream), nullptr, nullptr);
 }
 
-chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, size_t *bytes) {
+chebdav_status chebdav_orthonormalize_workspace_size(int64_t n, int ksub, int kb, chebdav_orth method,
+                                                     size_t *bytes) {
     if (!bytes || n < 1 || ksub < 0 || kb < 1) return fail(CHEBDAV_EINVAL, "bad arguments");
-    *bytes = orth_ws_bytes(n, ksub, kb);
+    if (method != CHEBDAV_ORTH_CHOLQR && method != CHEBDAV_ORTH_TSQR) return fail(CHEBDAV_EINVAL, "bad method");
+    if (method == CHEBDAV_ORTH_TSQR) {
+        size_t tb = 0;
+        CD_TRY(tsqr_ws_bytes(n, kb, &tb));
+    }
+    *bytes = orth_ws_bytes(n, ksub, kb, method);
+    return CHEBDAV_OK;
+}
+
+chebdav_status chebdav_tsqr_workspace_size(int64_t n, int kb, size_t *bytes) {
+    if (!bytes) return fail(CHEBDAV_EINVAL, "bytes is NULL");
+    return tsqr_ws_bytes(n, kb, bytes);
+}
+
+chebdav_status chebdav_tsqr(const double *X, int64_t ldx, int64_t n, int kb, double *Q, int64_t ldq,
+                            double *R, int64_t ldr, void *workspace, size_t ws_bytes, void *hip_stream) {
+    if (!X || !Q || !R) return fail(CHEBDAV_EINVAL, "NULL argument");
+    if (Q == X && ldq != ldx) return fail(CHEBDAV_EINVAL, "Q == X needs ldq == ldx");
+    hipStream_t st = as_stream(hip_stream);
+    CD_TRY(tsqr_factor(X, ldx, n, kb, Q, ldq, R, ldr, workspace, ws_bytes, st));
+    CD_TRY(tsqr_form_q(n, kb, Q, ldq, Q, ldq, workspace, ws_bytes, st));
     return CHEBDAV_OK;
 }
 
 chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, double *X,
                                       int64_t ldx, int kb, int64_t n, uint64_t seed,
-                                      uint64_t first_random_col, int *n_replaced,
+                                      uint64_t first_random_col, chebdav_orth method, int *n_replaced,
                                       void *workspace, size_t ws_bytes, void *hip_stream) {
     if (!X || n < 1 || kb < 1 || ksub < 0 || ldx < kb) return fail(CHEBDAV_EINVAL, "bad arguments");
     if (ksub > 0 && (!V || ldv < ksub)) return fail(CHEBDAV_EINVAL, "bad basis V");
@@ -168,7 +189,7 @@ chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, do
     uint64_t next = first_random_col;
     int rep = 0;
     hipStream_t st = as_stream(hip_stream);
-    CD_TRY(orthonormalize(v, X, ldx, kb, n, seed, &next, &rep, workspace, ws_bytes, st));
+    CD_TRY(orthonormalize(v, X, ldx, kb, n, seed, &next, &rep, workspace, ws_bytes, st, method));
     CD_HIP(hipStreamSynchronize(st));
     if (n_replaced) *n_replaced = rep;
     return CHEBDAV_OK;

@@ -172,10 +172,21 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
                          int64_t ldy, void *ws, size_t ws_bytes, hipStream_t st);
 
 // ---- orth.hip
-size_t orth_ws_bytes(int64_t n, int ksub, int kb);
+size_t orth_ws_bytes(int64_t n, int ksub, int kb, chebdav_orth method = CHEBDAV_ORTH_CHOLQR);
 chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int64_t n,
                               uint64_t seed, uint64_t *next_col, int *n_replaced, void *ws,
-                              size_t ws_bytes, hipStream_t st);
+                              size_t ws_bytes, hipStream_t st, chebdav_orth method = CHEBDAV_ORTH_CHOLQR);
+
+// ---- tsqr.hip (Householder TSQR)
+chebdav_status tsqr_ws_bytes(int64_t n, int kb, size_t *bytes);
+// Reflectors of the leaf level to Vleaf (ldv; may be X with the same ld), the
+// rest to ws; R (ldr, may be null) gets the R factor with a non-negative diagonal.
+chebdav_status tsqr_factor(const double *X, int64_t ldx, int64_t n, int kb, double *Vleaf, int64_t ldv, double *R,
+                           int64_t ldr, void *ws, size_t ws_bytes, hipStream_t st);
+// Q (ldq; may be Vleaf with the same ld) from the reflectors of tsqr_factor.
+chebdav_status tsqr_form_q(int64_t n, int kb, const double *Vleaf, int64_t ldv, double *Q, int64_t ldq, void *ws,
+                           size_t ws_bytes, hipStream_t st);
+chebdav_status tsqr_dep(const double *R, int64_t ldr, int kb, const double *norm0, int *dep, hipStream_t st);
 
 // ---- gcn.hip (learned warm start)
 size_t gcn_ws_bytes(int64_t n, const int dims[4]);

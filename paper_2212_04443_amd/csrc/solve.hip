@@ -41,6 +41,7 @@ struct Resolved {
     int k_want, kb, m, itmax, act_max, dim_max, k_ri, lmax;
     double tol, upperb, lowb, low_nwb0, f32_switch_tol;
     chebdav_dtype fdt;
+    chebdav_orth orth;
     uint64_t seed;
     bool timing;
 };
@@ -62,6 +63,7 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
                      : p->low_nwb0;
     r.f32_switch_tol = p->f32_switch_tol > 0 ? p->f32_switch_tol : 1e-5;
     r.fdt = p->filter_dtype;
+    r.orth = p->orth;
     r.seed = p->seed;
     r.timing = p->timing != 0;
     r.lmax = r.k_want + r.kb;
@@ -75,6 +77,8 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
     if (r.act_max > 512) return fail(CHEBDAV_EUNSUPPORTED, "act_max > 512");
     if (!(r.lowb < r.low_nwb0 && r.low_nwb0 < r.upperb)) return fail(CHEBDAV_EINVAL, "need lowb < low_nwb0 < upperb");
     if (r.fdt != CHEBDAV_F64 && r.fdt != CHEBDAV_F32) return fail(CHEBDAV_EINVAL, "bad filter dtype");
+    if (r.orth != CHEBDAV_ORTH_CHOLQR && r.orth != CHEBDAV_ORTH_TSQR) return fail(CHEBDAV_EINVAL, "bad orth method");
+    if (r.orth == CHEBDAV_ORTH_TSQR && r.kb > 64) return fail(CHEBDAV_EUNSUPPORTED, "TSQR needs kb <= 64");
     return CHEBDAV_OK;
 }
 
@@ -114,7 +118,7 @@ Layout layout(Arena &a, int64_t n, const Resolved &r) {
     L.filt_b = std::max(filter_ws_bytes(n, r.kb, CHEBDAV_F64),
                         r.fdt == CHEBDAV_F32 ? filter_ws_bytes(n, r.kb, CHEBDAV_F32) : 0);
     L.filt = a.take<char>(L.filt_b);
-    L.orth_b = orth_ws_bytes(n, r.dim_max, r.kb);
+    L.orth_b = orth_ws_bytes(n, r.dim_max, r.kb, r.orth);
     L.orthw = a.take<char>(L.orth_b);
     L.eig_b = eig_ws_bytes(r.act_max);
     L.eigw = a.take<char>(L.eig_b);
@@ -258,7 +262,7 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         V.ld2 = am;
         V.p2 = kr;
         int nrep = 0;
-        CD_TRY(orthonormalize(V, Xnew, am, kb, n, r.seed, &next_col, &nrep, L.orthw, L.orth_b, st));
+        CD_TRY(orthonormalize(V, Xnew, am, kb, n, r.seed, &next_col, &nrep, L.orthw, L.orth_b, st, r.orth));
         S.n_replaced += nrep;
         S.n_random += nrep;
         if (r.timing) {
