@@ -160,13 +160,18 @@ __device__ inline double group_sum(double v) {
 // DPP row rotations) and publishes v; every thread forms its column sums of
 // A v (row rotations again; A is symmetric, so column sums are p), the row
 // groups publish p and their share of p^T v; every thread then updates its
-// entries.  Tiles whose rows or columns are all finished are skipped.
+// entries of the columns after k.  Tiles whose rows or columns are all finished
+// are skipped.  Nothing goes to global memory inside the loop (a store there
+// makes the next step wait for it): reflector k stays in column k below the
+// diagonal, which later steps no longer update, and d, e, tau stay in LDS until
+// the end.
 template <int P, int T>
 __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict__ H, int64_t ldh, int n,
                                                        double *__restrict__ Vh, double *__restrict__ d,
                                                        double *__restrict__ e, double *__restrict__ tau) {
     constexpr int NV = P * T;
     __shared__ double vs[NV], ps[NV], kp[P], scal[2];
+    __shared__ double sd[NV], se[NV], stau[NV];
     const int tid = threadIdx.x, pc = tid / P, pr = tid % P;
     double A[T][T];
 #pragma unroll
@@ -211,13 +216,17 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
                 double v = 0.0;
                 if (t != 0.0 && i > k && i < n) v = (i == k + 1) ? v0 : col[a];
                 vs[i] = v;
-                if (i > k && i < n) Vh[(int64_t)k * n + (i - k - 1)] = v;
+                if (i == k + 1) {  // column k keeps the reflector: v0 here, x below
+#pragma unroll
+                    for (int b = 0; b < T; ++b)
+                        if (b == bk) A[a][b] = v0;
+                }
             }
             if (pr == 0) {
                 scal[0] = t;
-                tau[k] = t;
-                e[k] = alpha;
-                d[k] = dk;
+                stau[k] = t;
+                se[k] = alpha;
+                sd[k] = dk;
             }
         }
         __syncthreads();
@@ -241,7 +250,8 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
 #pragma unroll
             for (int a = 0; a < T; ++a)
                 if (P * (a + 1) - 1 > k) sacc += A[a][b] * vr[a];
-            q[b] = t * group_sum<P>(sacc);
+            const double gs = group_sum<P>(sacc);
+            q[b] = (pc + P * b > k) ? t * gs : 0.0;  // finished columns hold reflectors
             kpart += q[b] * vc[b];
         }
 #pragma unroll
@@ -260,8 +270,22 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
             const double wr = ps[pr + P * a] - K * vr[a];
 #pragma unroll
             for (int b = 0; b < T; ++b)
-                if (P * (b + 1) - 1 > k) A[a][b] -= vr[a] * (q[b] - K * vc[b]) + wr * vc[b];
+                if (P * (b + 1) - 1 > k && pc + P * b > k) A[a][b] -= vr[a] * (q[b] - K * vc[b]) + wr * vc[b];
         }
+    }
+    __syncthreads();
+    // reflectors (zero for an identity step), d, e, tau of the n - 2 steps
+#pragma unroll
+    for (int a = 0; a < T; ++a)
+#pragma unroll
+        for (int b = 0; b < T; ++b) {
+            const int i = pr + P * a, j = pc + P * b;
+            if (j + 2 < n && i > j && i < n) Vh[(int64_t)j * n + (i - j - 1)] = stau[j] != 0.0 ? A[a][b] : 0.0;
+        }
+    for (int k = tid; k + 2 < n; k += P * P) {
+        d[k] = sd[k];
+        e[k] = se[k];
+        tau[k] = stau[k];
     }
     // trailing 2 x 2 block (or the 1 x 1 matrix)
 #pragma unroll
@@ -290,14 +314,31 @@ __device__ inline double recip(double q) {
     return fma(r, fma(-q, r, 1.0), r);
 }
 
-// Number of eigenvalues of T smaller than x (Sturm sequence).
-__device__ inline int sturm(const double *d, const double *e, int n, double x, double pivmin) {
+// Number of eigenvalues of T smaller than x (Sturm sequence), from d and the
+// squared off-diagonal e2 (e2[i] = e[i]^2) in LDS; eight entries are read ahead
+// of the recurrence, whose latency then sets the pace.
+__device__ inline int sturm(const double *d, const double *e2, int n, double x, double pivmin) {
     int c = 0;
     double q = d[0] - x;
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
-    for (int i = 1; i < n; ++i) {
-        q = d[i] - x - (e[i - 1] * e[i - 1]) * recip(q);
+    int i = 1;
+    for (; i + 7 < n; i += 8) {
+        double dv[8], ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dv[u] = d[i + u];
+            ev[u] = e2[i + u - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            q = dv[u] - x - ev[u] * recip(q);
+            if (fabs(q) < pivmin) q = -pivmin;
+            c += q < 0.0;
+        }
+    }
+    for (; i < n; ++i) {
+        q = d[i] - x - e2[i - 1] * recip(q);
         if (fabs(q) < pivmin) q = -pivmin;
         c += q < 0.0;
     }
@@ -309,6 +350,12 @@ __device__ inline int sturm(const double *d, const double *e, int n, double x, d
 // the first sub-interval whose right end has more than j eigenvalues below it.
 __global__ void __launch_bounds__(256) k_bisect(const double *__restrict__ d, const double *__restrict__ e,
                                                 int n, double *__restrict__ w, double *__restrict__ par) {
+    __shared__ double sd[kMaxN], se2[kMaxN];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        sd[i] = d[i];
+        se2[i] = i + 1 < n ? e[i] * e[i] : 0.0;
+    }
+    __syncthreads();
     const int lane = lane_id();
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
@@ -333,7 +380,7 @@ __global__ void __launch_bounds__(256) k_bisect(const double *__restrict__ d, co
     for (int round = 0; round < 64; ++round) {
         if (hi - lo <= atol) break;
         const double x = lo + (hi - lo) * ((double)(lane + 1) / (double)(kWave + 1));
-        const bool above = sturm(d, e, n, x, pivmin) > j;
+        const bool above = sturm(sd, se2, n, x, pivmin) > j;
         const uint64_t mask = __ballot(above);
         const double xprev = __shfl_up(x, 1, kWave);
         if (mask == 0ull) {
