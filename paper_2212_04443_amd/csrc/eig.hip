@@ -260,9 +260,8 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
         if (pr == 0) kp[pc] = kpart;
         __syncthreads();
         // w = p - (t/2)(p^T v) v;  A <- A - v w^T - w v^T
-        double ktot = 0.0;
-#pragma unroll
-        for (int g = 0; g < P; ++g) ktot += kp[g];
+        // p^T v: the P row-group shares, summed across the P lanes of a group
+        const double ktot = group_sum<P>(kp[pr]);
         const double K = 0.5 * t * ktot;
 #pragma unroll
         for (int a = 0; a < T; ++a) {
@@ -449,12 +448,11 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
     double *rdd = sm + 5 * n;
     if (lane == 0) {
         // LU with partial pivoting of the tridiagonal T - lam I; the running
-        // diagonal and superdiagonal entries are carried in registers
+        // diagonal and superdiagonal entries are carried in registers.  The
+        // loops below read eight entries ahead into registers (the arrays share
+        // one LDS buffer, so the compiler cannot move reads above the writes).
         double ddi = dd[0], dui = du[0];
-        for (int i = 0; i + 1 < n; ++i) {
-            const double b = dl[i];
-            const double ddn = dd[i + 1];
-            const double dun = i + 2 < n ? du[i + 1] : 0.0;
+        auto lu_step = [&](int i, double b, double ddn, double dun) {
             if (fabs(ddi) >= fabs(b)) {
                 ipiv[i] = i;
                 const double piv = ddi != 0.0 ? ddi : tiny;
@@ -474,7 +472,20 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
                 if (i + 2 < n) du2[i] = dun;
                 dui = -f * dun;
             }
+        };
+        int i = 0;
+        for (; i + 9 < n; i += 8) {
+            double bl[8], dn[8], un[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                bl[u] = dl[i + u];
+                dn[u] = dd[i + u + 1];
+                un[u] = du[i + u + 1];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) lu_step(i + u, bl[u], dn[u], un[u]);
         }
+        for (; i + 1 < n; ++i) lu_step(i, dl[i], dd[i + 1], i + 2 < n ? du[i + 1] : 0.0);
         dd[n - 1] = ddi != 0.0 ? ddi : tiny;
     }
     __syncthreads();
@@ -484,26 +495,56 @@ __global__ void __launch_bounds__(64) k_inviter(const double *__restrict__ d, co
         if (lane == 0) {
             // forward elimination with the row interchanges (x[i] carried in a register)
             double xi = x[0];
-            for (int i = 0; i + 1 < n; ++i) {
-                const double f = dl[i];
-                const double xn = x[i + 1];
-                if (ipiv[i] == i) {
+            auto fwd_step = [&](int i, double f, double xn, int pv) {
+                if (pv == i) {
                     x[i] = xi;
                     xi = xn - f * xi;
                 } else {
                     x[i] = xn;
                     xi = xi - f * xn;
                 }
+            };
+            int i = 0;
+            for (; i + 8 < n; i += 8) {
+                double fv[8], xv[8];
+                int pv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    fv[u] = dl[i + u];
+                    xv[u] = x[i + u + 1];
+                    pv[u] = ipiv[i + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) fwd_step(i + u, fv[u], xv[u], pv[u]);
             }
+            for (; i + 1 < n; ++i) fwd_step(i, dl[i], x[i + 1], ipiv[i]);
             x[n - 1] = xi;
             // back substitution with U (diagonal dd, superdiagonals du, du2)
             double xb = x[n - 1] * rdd[n - 1];
             x[n - 1] = xb;
             double xa = (x[n - 2] - du[n - 2] * xb) * rdd[n - 2];
             x[n - 2] = xa;
-            for (int i = n - 3; i >= 0; --i) {
-                const double xv = (x[i] - du[i] * xa - du2[i] * xb) * rdd[i];
-                x[i] = xv;
+            int r = n - 3;
+            for (; r - 7 >= 0; r -= 8) {
+                double xr[8], dv[8], d2[8], rv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    xr[u] = x[r - u];
+                    dv[u] = du[r - u];
+                    d2[u] = du2[r - u];
+                    rv[u] = rdd[r - u];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const double xv = (xr[u] - dv[u] * xa - d2[u] * xb) * rv[u];
+                    x[r - u] = xv;
+                    xb = xa;
+                    xa = xv;
+                }
+            }
+            for (; r >= 0; --r) {
+                const double xv = (x[r] - du[r] * xa - du2[r] * xb) * rdd[r];
+                x[r] = xv;
                 xb = xa;
                 xa = xv;
             }
@@ -558,49 +599,61 @@ __global__ void __launch_bounds__(256) k_cluster_mgs(const double *__restrict__ 
 }
 
 // Y(:, j) = Q z_j with Q = H_0 H_1 ... H_{n-3}; one wavefront per eigenvector.
+// The reflectors are loaded D steps ahead of their use (a ring of D register
+// blocks) and tau sits in registers, read out lane by lane, so that a step
+// waits on neither memory nor the scalar cache.
 template <int kTpl>
 __global__ void __launch_bounds__(256) k_backtransform(const double *__restrict__ Vh,
                                                        const double *__restrict__ tau,
                                                        const double *__restrict__ Zv, int n,
                                                        double *__restrict__ Y, int64_t ldy) {
+    constexpr int D = kTpl <= 2 ? 8 : kTpl <= 4 ? 4 : 2;
     const int j = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (j >= n) return;
     const int lane = lane_id();
-    constexpr int tpl = kTpl;  // n <= 64 kTpl
-    double z[kTpl];
+    double z[kTpl], tl[kTpl];
 #pragma unroll
     for (int t = 0; t < kTpl; ++t) {
         const int i = lane + t * kWave;
-        z[t] = (t < tpl && i < n) ? Zv[(int64_t)j * n + i] : 0.0;
+        z[t] = i < n ? Zv[(int64_t)j * n + i] : 0.0;
+        tl[t] = i + 2 < n ? tau[i] : 0.0;
     }
-    double vc[kTpl], vn[kTpl];
     auto load_v = [&](int k, double (&dst)[kTpl]) {
         const double *vk = Vh + (int64_t)k * n - (k + 1);  // vk[i] for i in [k+1, n)
 #pragma unroll
         for (int t = 0; t < kTpl; ++t) {
             const int i = lane + t * kWave;
-            dst[t] = (t < tpl && i > k && i < n) ? vk[i] : 0.0;
+            dst[t] = (i > k && i < n) ? vk[i] : 0.0;
         }
     };
-    if (n >= 3) load_v(n - 3, vc);
-    for (int k = n - 3; k >= 0; --k) {
-        const double tk = tau[k];
-        if (k > 0) load_v(k - 1, vn);
-        if (tk != 0.0) {
-            double dot = 0.0;
+    double vb[D][kTpl];
 #pragma unroll
-            for (int t = 0; t < kTpl; ++t) dot += vc[t] * z[t];
-            const double sfac = tk * wave_sum(dot);
+    for (int u = 0; u < D; ++u)
+        if (n - 3 - u >= 0) load_v(n - 3 - u, vb[u]);
+    for (int k = n - 3; k >= 0; k -= D) {
 #pragma unroll
-            for (int t = 0; t < kTpl; ++t) z[t] -= sfac * vc[t];
+        for (int u = 0; u < D; ++u) {
+            const int kk = k - u;
+            if (kk < 0) break;
+            double tv = tl[0];
+#pragma unroll
+            for (int t = 1; t < kTpl; ++t) tv = (t == (kk >> 6)) ? tl[t] : tv;
+            const double tk = read_lane(tv, kk & (kWave - 1));
+            if (tk != 0.0) {
+                double dot = 0.0;
+#pragma unroll
+                for (int t = 0; t < kTpl; ++t) dot += vb[u][t] * z[t];
+                const double sfac = tk * wave_sum(dot);
+#pragma unroll
+                for (int t = 0; t < kTpl; ++t) z[t] -= sfac * vb[u][t];
+            }
+            if (kk - D >= 0) load_v(kk - D, vb[u]);
         }
-#pragma unroll
-        for (int t = 0; t < kTpl; ++t) vc[t] = vn[t];
     }
 #pragma unroll
     for (int t = 0; t < kTpl; ++t) {
         const int i = lane + t * kWave;
-        if (t < tpl && i < n) Y[(int64_t)i * ldy + j] = z[t];
+        if (i < n) Y[(int64_t)i * ldy + j] = z[t];
     }
 }
 
