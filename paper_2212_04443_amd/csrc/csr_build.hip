@@ -247,6 +247,13 @@ __global__ void __launch_bounds__(kLongBlock) k_sort_long(const int64_t *__restr
     if (threadIdx.x == 0) ucnt[r] = (int32_t)carry;
 }
 
+// nval[e] = dinv[col[e]]
+__global__ void k_nval(const int32_t *__restrict__ col, const double *__restrict__ dinv, double *__restrict__ nval,
+                       int64_t nnz) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += stride) nval[e] = dinv[col[e]];
+}
+
 // dinv = 1/sqrt(deg) with IEEE round-to-nearest sqrt and division; 0 for deg 0.
 __device__ inline double dinv_of(int32_t d) { return d > 0 ? 1.0 / sqrt((double)d) : 0.0; }
 
@@ -332,6 +339,7 @@ void free_graph(Graph *g) {
     if (g->deg) (void)hipFree(g->deg);
     if (g->dinv) (void)hipFree(g->dinv);
     if (g->dinv32) (void)hipFree(g->dinv32);
+    if (g->nval) (void)hipFree(g->nval);
     delete g;
 }
 
@@ -465,6 +473,20 @@ chebdav_status build_graph(const int64_t *edges, int64_t E, int64_t n, int on_de
     }
     g->n_isolated = hstats[0];
     g->max_deg = hstats[1];
+    // dinv of every nonzero's column, in CSR order: the plain product streams it
+    // with the column indices instead of gathering dinv per neighbour
+    if (hipMalloc(&g->nval, sizeof(double) * std::max<int64_t>(nnz, 1)) != hipSuccess) {
+        cleanup();
+        return fail(CHEBDAV_ENOMEM, "allocation failed (%lld nonzero scalings)", (long long)nnz);
+    }
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_nval, dim3((unsigned)std::min<int64_t>(ceil_div(nnz, 256), 65536)), dim3(256), 0, st,
+                           g->col, g->dinv, g->nval, nnz);
+        if (hipGetLastError() != hipSuccess) {
+            cleanup();
+            return fail(CHEBDAV_EHIP, "nonzero scalings failed");
+        }
+    }
     // per-XCD row ranges for the sparse step (bsum has room: nb >= 1 entries, use counters' buffer)
     {
         int64_t *d_split = static_cast<int64_t *>(lists.p);  // 2n >= 9 entries unless n < 5

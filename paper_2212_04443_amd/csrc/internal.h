@@ -50,6 +50,7 @@ struct Graph {
     int32_t *deg = nullptr;      // [n]
     double *dinv = nullptr;      // [n]
     float *dinv32 = nullptr;     // [n], dinv rounded to FP32 (for the FP32 filter)
+    double *nval = nullptr;      // [nnz], dinv of each nonzero's column (streamed by the plain product)
     // Row ranges of the sparse step per XCD: XCD x owns rows [xcd_row[x], xcd_row[x+1]),
     // chosen so that nnz + 4 * rows is about equal across the eight XCDs.
     int64_t xcd_row[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};

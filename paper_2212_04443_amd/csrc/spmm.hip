@@ -66,14 +66,16 @@ struct Chunk {
     static constexpr int UNR = CH < 8 ? CH : 8;
 };
 
-// NBR = true: the neighbour rows are scaled by their dinv (the plain product);
+// NBR = true: the neighbour rows are scaled by their dinv (the plain product),
+// streamed per nonzero from nval (CSR order) with the column indices;
 // NBR = false: the block is already scaled by s = dinv (1 on isolated rows), so
 // the neighbour rows are summed as they are and the row sum takes dinv_i^2.
 // flags (kStep*): the output times s_i or divided by s_i, Z times s_i.
 template <typename T, typename TO, int VE, int G, bool NBR>
 __global__ void __launch_bounds__(kBlock)
     k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
-                const T *__restrict__ dinv, T alpha, T beta, T gamma, const T *__restrict__ U,
+                const double *__restrict__ nval, const T *__restrict__ dinv, T alpha, T beta, T gamma,
+                const T *__restrict__ U,
                 int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
                 int w, XcdRanges xr, int flags) {
     constexpr int GPB = kBlock / G;  // rows per block
@@ -102,20 +104,22 @@ __global__ void __launch_bounds__(kBlock)
     const T di = dinv[r];
 
     int jl[PER];
+    T dl[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int64_t idx = beg + gl + (int64_t)k * G;
         jl[k] = idx < end ? col[idx] : 0;
+        if constexpr (NBR) dl[k] = idx < end ? (T)nval[idx] : T(0);
     }
     for (int64_t base = beg; base < end; base += CH) {
         const int cnt = (int)min<int64_t>(CH, end - base);
         int jn[PER];
-        T dl[PER];
+        T dn[PER];
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             const int64_t nidx = base + CH + gl + (int64_t)k * G;
             jn[k] = nidx < end ? col[nidx] : 0;
-            if constexpr (NBR) dl[k] = (base + gl + (int64_t)k * G) < end ? dinv[jl[k]] : T(0);
+            if constexpr (NBR) dn[k] = nidx < end ? (T)nval[nidx] : T(0);
         }
         for (int t0 = 0; t0 < cnt; t0 += UNR) {
             T u[UNR][VE];
@@ -144,7 +148,10 @@ __global__ void __launch_bounds__(kBlock)
             }
         }
 #pragma unroll
-        for (int k = 0; k < PER; ++k) jl[k] = jn[k];
+        for (int k = 0; k < PER; ++k) {
+            jl[k] = jn[k];
+            if constexpr (NBR) dl[k] = dn[k];
+        }
     }
     if (!active) return;
     TO *yp = Y + r * ldy + c0;
@@ -187,7 +194,7 @@ chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *
 #define CD_CASE(GG)                                                                                 \
     case GG:                                                                                        \
         hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG, NBR>), gr, bl, 0, st, g->n, g->row_ptr, g->col, \
-                           dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr, flags);                    \
+                           g->nval, dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr, flags);           \
         break;
     switch (G) {
         CD_CASE(1)
