@@ -42,7 +42,8 @@ typedef enum {
 typedef enum { CHEBDAV_F64 = 0, CHEBDAV_F32 = 1 } chebdav_dtype;
 
 /* Orthonormalization of a new block after its projections (Alg. 2 step 6):
- * Cholesky QR twice, or Householder TSQR (Sec. 5). */
+ * Cholesky QR with a second pass (Cholesky QR or a Newton-Schulz step), or
+ * Householder TSQR (Sec. 5). */
 typedef enum { CHEBDAV_ORTH_CHOLQR = 0, CHEBDAV_ORTH_TSQR = 1 } chebdav_orth;
 
 /* Opaque handle owning the device CSR pattern of S and its degree scaling. */
@@ -125,11 +126,13 @@ chebdav_status chebdav_filter(const chebdav_graph *g, const double *X, int64_t l
  * columns of V (n x ksub, device double, row-major, ldv; may be NULL if
  * ksub == 0), and spans the same space as (I - V V^T) X_in when that has full
  * numerical rank.  Method: two block classical Gram-Schmidt passes against V,
- * then (method CHOLQR) Cholesky QR with a dependence test, then a third pass
- * against V only when the smallest diagonal entry of the scaled Cholesky factor
- * is below 0.01, and a second Cholesky QR; or (method TSQR) the same with
- * Householder TSQR (chebdav_tsqr) in place of each Cholesky QR, its R deciding
- * dependence with the same thresholds.  A column whose norm after projection
+ * then (method CHOLQR) Cholesky QR with a dependence test; when the smallest
+ * diagonal entry of the scaled Cholesky factor is below 0.01, a third pass
+ * against V and a second Cholesky QR, otherwise one Newton-Schulz step
+ * X <- X (3 I - X^T X) / 2 (X^T X is then within O(1e4 eps) of I, and the step
+ * squares that deviation); or (method TSQR) the same with Householder TSQR
+ * (chebdav_tsqr) in place of each Cholesky QR, its R deciding dependence with
+ * the same thresholds, and no second pass unless the third projection ran.  A column whose norm after projection
  * is below 1e-10 of its norm before, or whose squared pivot in the
  * column-scaled factor is below 1e-13, is numerically dependent and replaced
  * by a Philox4x32-10 column (key = seed, counters numbered from

@@ -657,13 +657,6 @@ __global__ void __launch_bounds__(256) k_backtransform(const double *__restrict_
     }
 }
 
-__global__ void k_ns_prep(const double *__restrict__ G, int n, double *__restrict__ B) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)n * n) return;
-    const int i = (int)(q / n), j = (int)(q % n);
-    B[q] = (i == j ? 1.5 : 0.0) - 0.5 * G[q];
-}
-
 __global__ void k_copy_vec(const double *__restrict__ s, double *__restrict__ d, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) d[i] = s[i];
@@ -738,8 +731,7 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
         stt.ld1 = n;
         stt.p1 = n;
         CD_TRY(gram(stt, s.T, n, n, n, s.G, n, s.part, st));
-        hipLaunchKernelGGL(k_ns_prep, dim3(gnn), dim3(256), 0, st, s.G, n, s.Bm);
-        CD_LAUNCH_CHECK();
+        CD_TRY(ns_matrix(s.G, n, s.Bm, st));
         CD_TRY(update(stt, s.Bm, n, 1.0, 0.0, Y, ldy, n, n, st));
     }
     hipLaunchKernelGGL(k_copy_vec, dim3(g64), dim3(64), 0, st, s.w, evals, n);

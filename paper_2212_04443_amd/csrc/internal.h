@@ -164,6 +164,8 @@ chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStr
 // Q <- [[Q, 0], [0, I]] Y.
 chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
                          hipStream_t st);
+// B = (3 I - G) / 2 (n x n, contiguous): one Newton-Schulz orthonormalization step.
+chebdav_status ns_matrix(const double *G, int n, double *B, hipStream_t st);
 chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
                             int nc, double *Qn, int64_t ldn, hipStream_t st);
 

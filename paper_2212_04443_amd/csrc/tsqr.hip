@@ -25,7 +25,6 @@
 // where d_c is the product of the rows >= j of columns j and c.  A column that
 // is zero from row j down gets tau = 0 (no reflection) and R_jj = 0.
 #include <algorithm>
-#include <vector>
 
 #include "device_util.h"
 #include "internal.h"
