@@ -31,51 +31,68 @@ __device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// Partial Gram on matrix cores: one wavefront computes the 64 x (16 TQT) tile
-// (i0.., j0..) of Xs^T Y over the rows of split z, four rows per MFMA step and
-// 4 UR rows per loop trip (all their loads issued before the MFMAs), with both
-// operands loaded straight from the row-major blocks (lane k*16 + c reads
-// column c of row k: four 128-byte row segments per load).
-template <int TQT, int UR>
+// Partial Gram on matrix cores: one wavefront computes the (16 TP) x (16 TQT)
+// tile (i0.., j0..) of Xs^T Y over the rows of split z, four rows per MFMA step
+// and 4 UR rows per loop trip, with both operands loaded straight from the
+// row-major blocks (lane k*16 + c reads column c of row k: four 128-byte row
+// segments per load).  The loads of the next trip are issued before the MFMAs
+// of the current one (two register sets), so a wavefront always has a trip of
+// loads in flight.  TP = 2 serves p <= 32 without idle matrix-core work.
+template <int TP, int TQT, int UR>
 __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy, int q,
                                              int64_t n, int64_t rows_per_split, double *__restrict__ part) {
     const int p = xs.cols();
     const int lane = threadIdx.x;
     const int kr = lane >> 4, cc = lane & 15;
-    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * (16 * TQT);
+    const int i0 = blockIdx.x * (16 * TP), j0 = blockIdx.y * (16 * TQT);
     const int64_t r_beg = (int64_t)blockIdx.z * rows_per_split;
     const int64_t r_end = min(n, r_beg + rows_per_split);
-    d4_t acc[4][TQT];
+    d4_t acc[TP][TQT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TP; ++t)
 #pragma unroll
         for (int u = 0; u < TQT; ++u) acc[t][u] = d4_t{0.0, 0.0, 0.0, 0.0};
-    bool colv[4], colw[TQT];
+    bool colv[TP], colw[TQT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) colv[t] = i0 + 16 * t + cc < p;
+    for (int t = 0; t < TP; ++t) colv[t] = i0 + 16 * t + cc < p;
 #pragma unroll
     for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
-    for (int64_t r = r_beg; r < r_end; r += 4 * UR) {
-        double a[UR][4], b[UR][TQT];
+    auto load = [&](int64_t r, double (&a)[UR][TP], double (&b)[UR][TQT]) {
 #pragma unroll
         for (int h = 0; h < UR; ++h) {
             const int64_t row = r + 4 * h + kr;
             const bool rv = row < r_end;
 #pragma unroll
-            for (int t = 0; t < 4; ++t) a[h][t] = (rv && colv[t]) ? seg_load(xs, row, i0 + 16 * t + cc) : 0.0;
+            for (int t = 0; t < TP; ++t) a[h][t] = (rv && colv[t]) ? seg_load(xs, row, i0 + 16 * t + cc) : 0.0;
 #pragma unroll
             for (int u = 0; u < TQT; ++u) b[h][u] = (rv && colw[u]) ? Y[row * ldy + j0 + 16 * u + cc] : 0.0;
         }
+    };
+    auto trip = [&](double (&a)[UR][TP], double (&b)[UR][TQT]) {
 #pragma unroll
         for (int h = 0; h < UR; ++h)
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int t = 0; t < TP; ++t)
 #pragma unroll
                 for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
+    };
+    constexpr int64_t step = 4 * UR;
+    double a0[UR][TP], b0[UR][TQT], a1[UR][TP], b1[UR][TQT];
+    int64_t r = r_beg;
+    if (r < r_end) load(r, a0, b0);
+    while (r < r_end) {
+        const int64_t r1 = r + step;
+        if (r1 < r_end) load(r1, a1, b1);
+        trip(a0, b0);
+        if (r1 >= r_end) break;
+        const int64_t r2 = r1 + step;
+        if (r2 < r_end) load(r2, a0, b0);
+        trip(a1, b1);
+        r = r2;
     }
     double *out = part + (int64_t)blockIdx.z * p * q;
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TP; ++t)
 #pragma unroll
         for (int u = 0; u < TQT; ++u)
 #pragma unroll
@@ -302,13 +319,23 @@ chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t
     const int splits = gram_splits(n, p, q);
     const int64_t rps = ceil_div(ceil_div(n, splits), 16) * 16;
     const int qt = std::min(q, TB);
-    const dim3 grid((unsigned)ceil_div(p, TB), (unsigned)ceil_div(q, qt), (unsigned)splits);
-    if (qt <= 16)
-        hipLaunchKernelGGL((k_gram<1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
-    else if (qt <= 32)
-        hipLaunchKernelGGL((k_gram<2, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
-    else
-        hipLaunchKernelGGL((k_gram<4, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    const int pt = p <= 32 ? 32 : TB;  // X tile: 32 or 64 columns
+    const dim3 grid((unsigned)ceil_div(p, pt), (unsigned)ceil_div(q, qt), (unsigned)splits);
+    if (pt == 32) {
+        if (qt <= 16)
+            hipLaunchKernelGGL((k_gram<2, 1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else if (qt <= 32)
+            hipLaunchKernelGGL((k_gram<2, 2, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else
+            hipLaunchKernelGGL((k_gram<2, 4, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    } else {
+        if (qt <= 16)
+            hipLaunchKernelGGL((k_gram<4, 1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else if (qt <= 32)
+            hipLaunchKernelGGL((k_gram<4, 2, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else
+            hipLaunchKernelGGL((k_gram<4, 4, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+    }
     CD_LAUNCH_CHECK();
     const int64_t pq = (int64_t)p * q;
     hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 8)), dim3(256), 0, st, partial, splits, pq,
