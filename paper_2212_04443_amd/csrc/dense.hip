@@ -149,8 +149,9 @@ int gram_splits(int64_t n, int p, int q) {
 // Y = alpha Xs B + beta Y on matrix cores: one wavefront owns a 64-row x
 // (16 TQT)-column tile of Y, accumulates over all p columns of Xs (four per MFMA
 // step; lane k*16 + i reads row i, column k: consecutive lanes of a row read
-// adjacent elements; 4 UR columns per loop trip) and writes the tile only at
-// the end, so Y may alias Xs when it has a single column tile.
+// adjacent elements; 4 UR columns per loop trip, the next trip's loads issued
+// before the current trip's MFMAs) and writes the tile only at the end, so Y
+// may alias Xs when it has a single column tile.
 template <int TQT, int UR>
 __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
                                                double alpha, double beta, double *Y, int64_t ldy, int q,
@@ -170,8 +171,7 @@ __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict
     for (int t = 0; t < 4; ++t) rowv[t] = r0 + 16 * t + cc < n;
 #pragma unroll
     for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
-    for (int k0 = 0; k0 < p; k0 += 4 * UR) {
-        double a[UR][4], b[UR][TQT];
+    auto load = [&](int k0, double (&a)[UR][4], double (&b)[UR][TQT]) {
 #pragma unroll
         for (int h = 0; h < UR; ++h) {
             const int kk = k0 + 4 * h + kr;
@@ -181,12 +181,28 @@ __global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict
 #pragma unroll
             for (int u = 0; u < TQT; ++u) b[h][u] = (kv && colw[u]) ? B[(int64_t)kk * ldb + j0 + 16 * u + cc] : 0.0;
         }
+    };
+    auto trip = [&](double (&a)[UR][4], double (&b)[UR][TQT]) {
 #pragma unroll
         for (int h = 0; h < UR; ++h)
 #pragma unroll
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
+    };
+    constexpr int step = 4 * UR;
+    double a0[UR][4], b0[UR][TQT], a1[UR][4], b1[UR][TQT];
+    int k0 = 0;
+    load(0, a0, b0);
+    while (k0 < p) {
+        const int k1 = k0 + step;
+        if (k1 < p) load(k1, a1, b1);
+        trip(a0, b0);
+        if (k1 >= p) break;
+        const int k2 = k1 + step;
+        if (k2 < p) load(k2, a0, b0);
+        trip(a1, b1);
+        k0 = k2;
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -355,23 +371,12 @@ chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha
     }
     const int qt = std::min(q, TB);
     const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, qt));
-    const bool deep = Xs.cols() >= 64;  // longer sums: 32 columns per loop trip
-    if (qt <= 16) {
-        if (deep)
-            hipLaunchKernelGGL((k_update<1, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-        else
-            hipLaunchKernelGGL((k_update<1, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    } else if (qt <= 32) {
-        if (deep)
-            hipLaunchKernelGGL((k_update<2, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-        else
-            hipLaunchKernelGGL((k_update<2, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    } else {
-        if (deep)
-            hipLaunchKernelGGL((k_update<4, 8>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-        else
-            hipLaunchKernelGGL((k_update<4, 4>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    }
+    if (qt <= 16)
+        hipLaunchKernelGGL((k_update<1, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    else if (qt <= 32)
+        hipLaunchKernelGGL((k_update<2, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    else
+        hipLaunchKernelGGL((k_update<4, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
