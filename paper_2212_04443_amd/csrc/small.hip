@@ -10,7 +10,8 @@ constexpr int kMaxKb = 64;
 // Cholesky factor and inverse for Cholesky QR.  One workgroup of 256 threads on
 // a 16 x 16 grid; thread (ti, tj) owns the entries (ti + 16 a, tj + 16 b) of the
 // kb x kb working matrix in LDS, so every step updates all entries in parallel
-// without index arithmetic.
+// without index arithmetic.  Two barriers per step: the diagonal of R is kept
+// apart (dR), so a step's scaling never overwrites what other threads read.
 //   scaled = 1: x_j = sqrt(G_jj) is column j's norm after projection; it is
 //     dependent if x_j < 1e-10 * norm0_j (or not finite/positive).  The
 //     remaining columns are scaled to unit norm (Gt = S G S, S = diag(1/x)) and
@@ -30,7 +31,7 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
     // R in the upper triangle of A; B = R^{-1} (upper) kept transposed in the
     // strict lower triangle of A, its diagonal in bd
     __shared__ double A[kMaxKb][kMaxKb + 1];
-    __shared__ double bd[kMaxKb];
+    __shared__ double bd[kMaxKb], dR[kMaxKb];  // diagonals of R^{-1} and of R
     __shared__ double s[kMaxKb];
     __shared__ int d[kMaxKb + 2];
     const int tid = threadIdx.x, ti = tid / P, tj = tid % P;
@@ -66,10 +67,10 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
         const bool badp = !(pv > thr) || !isfinite(pv);
         if (badp) pv = 1.0;
         const double piv = sqrt(pv);
-        __syncthreads();
+        // R_kk goes to dR, so A[k][k] is not written while others read it
         if (tid == 0) {
             if (badp) d[k] = 1;
-            A[k][k] = piv;
+            dR[k] = piv;
         }
         if (tid > k && tid < kb) A[k][tid] /= piv;
         __syncthreads();
@@ -94,8 +95,7 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
     // Gauss-Jordan on [R | B] from the last row up: B(k, :) /= R_kk, then
     // B(i, :) -= R_ik B(k, :) for i < k; B ends as R^{-1}
     for (int k = kb - 1; k >= 0; --k) {
-        const double rk = 1.0 / A[k][k];
-        __syncthreads();
+        const double rk = 1.0 / dR[k];
         if (tid == k) bd[k] *= rk;
         if (tid > k && tid < kb) A[tid][k] *= rk;
         __syncthreads();
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
         double rmin = 1.0;
         for (int j = 0; j < kb; ++j) {
             any |= d[j];
-            if (!d[j]) rmin = fmin(rmin, A[j][j]);
+            if (!d[j]) rmin = fmin(rmin, dR[j]);
         }
         dep[kb] = any;
         dep[kb + 1] = rmin < 0.01;
@@ -160,42 +160,55 @@ __global__ void k_h_set_diag(double *__restrict__ H, int64_t ldh, const double *
     H[(int64_t)i * ldh + j] = (i == j) ? dg[i] : 0.0;
 }
 
-// Deferred rotation of the search basis.  The active block is kept as B Q:
-// B (n x kr, orthonormal, in HBM) and a small kr x ka matrix Q.
-// C(i, j) = sum_{r < kr} Q(r, i) Cf(r, j) for i < ka, and Cf(kr + i - ka, j) for
-// ka <= i < ka + kb: the new columns of H = [B Q, X]^T (A X) from Cf = [B, X]^T (A X).
-__global__ void k_proj_cols(const double *__restrict__ Q, int64_t ldq, const double *__restrict__ Cf,
-                            int kr, int ka, int kb, double *__restrict__ C) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (ka + kb) * kb) return;
-    const int i = e / kb, j = e % kb;
-    double t;
-    if (i < ka) {
-        t = 0.0;
-        for (int r = 0; r < kr; ++r) t += Q[(int64_t)r * ldq + i] * Cf[(int64_t)r * kb + j];
-    } else {
-        t = Cf[(int64_t)(kr + i - ka) * kb + j];
+// C (m x n, ldc) = op(A) B with op(A) = A (m x k, lda) or A^T (A is k x m, lda)
+// and B (k x n, ldb): 32 x 32 output tiles, 32-deep slices of both operands
+// staged in LDS with coalesced loads; every output sums over k in ascending
+// order.  For the small matrices of the deferred rotation (<= 512 on a side).
+template <bool TA>
+__global__ void __launch_bounds__(256) k_small_gemm(const double *__restrict__ A, int64_t lda,
+                                                    const double *__restrict__ B, int64_t ldb,
+                                                    double *__restrict__ C, int64_t ldc, int m, int n, int k) {
+    __shared__ double As[32][33], Bs[32][33];  // As[i][kk] = op(A)(i0 + i, k0 + kk)
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
+    const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < k; k0 += 32) {
+        for (int r = ty; r < 32; r += 8) {
+            if (TA) {  // A row k0 + r, columns i0 + tx
+                const int kk = k0 + r, i = i0 + tx;
+                As[tx][r] = (kk < k && i < m) ? A[(int64_t)kk * lda + i] : 0.0;
+            } else {   // A row i0 + r, columns k0 + tx
+                const int i = i0 + r, kk = k0 + tx;
+                As[r][tx] = (i < m && kk < k) ? A[(int64_t)i * lda + kk] : 0.0;
+            }
+            const int kk = k0 + r, j = j0 + tx;
+            Bs[r][tx] = (kk < k && j < n) ? B[(int64_t)kk * ldb + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < 32; ++kk) {
+            const double b = Bs[kk][tx];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += As[ty + 8 * q][kk] * b;
+        }
+        __syncthreads();
     }
-    C[e] = t;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int i = i0 + ty + 8 * q, j = j0 + tx;
+        if (i < m && j < n) C[(int64_t)i * ldc + j] = acc[q];
+    }
 }
 
-// Qn = [[Q, 0], [0, I_kb]] Y(:, 1:nc): rows r < kr take sum_{i < ka} Q(r, i) Y(i, j);
-// rows kr + t take Y(ka + t, j).
-__global__ void k_extend_basis(const double *__restrict__ Q, int64_t ldq, const double *__restrict__ Y,
-                               int64_t ldy, int kr, int ka, int kb, int nc, double *__restrict__ Qn,
-                               int64_t ldn) {
+// D(r, j) = S(r, j) for r < rows, j < cols
+__global__ void k_copy_rows(const double *__restrict__ S, int64_t lds, double *__restrict__ D, int64_t ldd, int rows,
+                            int cols) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)(kr + kb) * nc) return;
-    const int r = (int)(e / nc), j = (int)(e % nc);
-    double t;
-    if (r < kr) {
-        t = 0.0;
-        for (int i = 0; i < ka; ++i) t += Q[(int64_t)r * ldq + i] * Y[(int64_t)i * ldy + j];
-    } else {
-        t = Y[(int64_t)(ka + r - kr) * ldy + j];
-    }
-    Qn[(int64_t)r * ldn + j] = t;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), j = (int)(e % cols);
+    D[(int64_t)r * ldd + j] = S[(int64_t)r * lds + j];
 }
+
 
 }  // namespace
 
@@ -228,23 +241,40 @@ chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStr
     return CHEBDAV_OK;
 }
 
+// Deferred rotation of the search basis: the active block is kept as B Q, with
+// B (n x kr, orthonormal, in HBM) and a small kr x ka matrix Q.
+// New columns of H = [B Q, X]^T (A X) from Cf = [B, X]^T (A X):
+// C(0:ka, :) = Q(:, 0:ka)^T Cf(0:kr, :), C(ka + t, :) = Cf(kr + t, :) (t < kb); C is
+// (ka + kb) x kb contiguous.
 chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
                          hipStream_t st) {
-    const int total = (ka + kb) * kb;
-    if (total == 0) return CHEBDAV_OK;
-    hipLaunchKernelGGL(k_proj_cols, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, Q, ldq, Cf, kr, ka,
-                       kb, C);
+    if (kb == 0) return CHEBDAV_OK;
+    if (ka > 0) {
+        hipLaunchKernelGGL(k_small_gemm<true>, dim3((unsigned)ceil_div(kb, 32), (unsigned)ceil_div(ka, 32)), dim3(256), 0,
+                           st, Q, ldq, Cf, (int64_t)kb, C, (int64_t)kb, ka, kb, kr);
+        CD_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div((int64_t)kb * kb, 256)), dim3(256), 0, st,
+                       Cf + (int64_t)kr * kb, (int64_t)kb, C + (int64_t)ka * kb, (int64_t)kb, kb, kb);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
 
+// Qn = [[Q, 0], [0, I_kb]] Y(:, 0:nc): Qn(0:kr, :) = Q(0:kr, 0:ka) Y(0:ka, 0:nc),
+// Qn(kr + t, :) = Y(ka + t, 0:nc) (t < kb).
 chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
                             int nc, double *Qn, int64_t ldn, hipStream_t st) {
-    const int64_t total = (int64_t)(kr + kb) * nc;
-    if (total == 0) return CHEBDAV_OK;
-    hipLaunchKernelGGL(k_extend_basis, dim3((unsigned)ceil_div(total, 256)), dim3(256), 0, st, Q, ldq, Y, ldy,
-                       kr, ka, kb, nc, Qn, ldn);
-    CD_LAUNCH_CHECK();
+    if (nc == 0) return CHEBDAV_OK;
+    if (kr > 0) {
+        hipLaunchKernelGGL(k_small_gemm<false>, dim3((unsigned)ceil_div(nc, 32), (unsigned)ceil_div(kr, 32)), dim3(256), 0,
+                           st, Q, ldq, Y, ldy, Qn, ldn, kr, nc, ka);
+        CD_LAUNCH_CHECK();
+    }
+    if (kb > 0) {
+        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div((int64_t)kb * nc, 256)), dim3(256), 0, st,
+                           Y + (int64_t)ka * ldy, ldy, Qn + (int64_t)kr * ldn, ldn, kb, nc);
+        CD_LAUNCH_CHECK();
+    }
     return CHEBDAV_OK;
 }
 
