@@ -157,7 +157,7 @@ def torch_sync():
     torch.cuda.synchronize()
 
 
-def measured_traffic(workload, kb):
+def measured_traffic(workload, kb, n):
     """HBM bytes per FP64 k_cheb_step launch from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a plain
     1 GiB copy), or None if the kernel source changed since it was taken."""
@@ -169,8 +169,11 @@ def measured_traffic(workload, kb):
     src = open(os.path.join(ROOT, "paper_2212_04443_amd", "csrc", "spmm.hip"), "rb").read()
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
         return None
-    # the filter's interior steps (scaled variables) dominate: m - 1 of its m launches
-    k = rec.get("kernels", {}).get("k_cheb_step<double, double, 2, %d, false>" % (kb * 8 // 16))
+    # the filter's interior steps (scaled variables) dominate: m - 1 of its m launches;
+    # the library takes deep batches once the gathered block exceeds 256 MiB
+    deep = kb >= 16 and n * kb * 8 > 256 * 1024 * 1024
+    k = rec.get("kernels", {}).get("k_cheb_step<double, double, 2, %d, false, %s>"
+                                   % (kb * 8 // 16, "true" if deep else "false"))
     return None if k is None else k["traffic_bytes_per_launch"]
 
 
@@ -269,7 +272,7 @@ def main():
     s = 8 if forms[0] == "f64" else 4
     bstep = bytes_per_step(n, g.nnz, kb, 8)     # FP64 steps (the primary path)
     achieved = bstep / (prim["filter_ms_per_launch"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, kb) if forms[0] == "f64" else None
+    traffic = measured_traffic(args.workload, kb, n) if forms[0] == "f64" else None
     line = {
         "metric": METRIC,
         "value": prim["seconds"],

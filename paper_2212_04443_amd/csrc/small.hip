@@ -163,16 +163,19 @@ __global__ void k_h_set_diag(double *__restrict__ H, int64_t ldh, const double *
 // C (m x n, ldc) = op(A) B with op(A) = A (m x k, lda) or A^T (A is k x m, lda)
 // and B (k x n, ldb): 32 x 32 output tiles, 32-deep slices of both operands
 // staged in LDS with coalesced loads; every output sums over k in ascending
-// order.  For the small matrices of the deferred rotation (<= 512 on a side).
+// order.  Rows m .. m + mc - 1 of C are copied from S (lds) rows 0 .. mc - 1.
+// For the small matrices of the deferred rotation (<= 512 on a side).
 template <bool TA>
 __global__ void __launch_bounds__(256) k_small_gemm(const double *__restrict__ A, int64_t lda,
                                                     const double *__restrict__ B, int64_t ldb,
-                                                    double *__restrict__ C, int64_t ldc, int m, int n, int k) {
+                                                    double *__restrict__ C, int64_t ldc, int m, int n, int k,
+                                                    const double *__restrict__ S, int64_t lds, int mc) {
     __shared__ double As[32][33], Bs[32][33];  // As[i][kk] = op(A)(i0 + i, k0 + kk)
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;
     const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < k; k0 += 32) {
+    const int kend = i0 < m ? k : 0;  // blocks wholly in the copied rows skip the product
+    for (int k0 = 0; k0 < kend; k0 += 32) {
         for (int r = ty; r < 32; r += 8) {
             if (TA) {  // A row k0 + r, columns i0 + tx
                 const int kk = k0 + r, i = i0 + tx;
@@ -196,19 +199,13 @@ __global__ void __launch_bounds__(256) k_small_gemm(const double *__restrict__ A
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int i = i0 + ty + 8 * q, j = j0 + tx;
-        if (i < m && j < n) C[(int64_t)i * ldc + j] = acc[q];
+        if (j >= n) continue;
+        if (i < m)
+            C[(int64_t)i * ldc + j] = acc[q];
+        else if (i < m + mc)
+            C[(int64_t)i * ldc + j] = S[(int64_t)(i - m) * lds + j];
     }
 }
-
-// D(r, j) = S(r, j) for r < rows, j < cols
-__global__ void k_copy_rows(const double *__restrict__ S, int64_t lds, double *__restrict__ D, int64_t ldd, int rows,
-                            int cols) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (int64_t)rows * cols) return;
-    const int r = (int)(e / cols), j = (int)(e % cols);
-    D[(int64_t)r * ldd + j] = S[(int64_t)r * lds + j];
-}
-
 
 }  // namespace
 
@@ -249,13 +246,9 @@ chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStr
 chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
                          hipStream_t st) {
     if (kb == 0) return CHEBDAV_OK;
-    if (ka > 0) {
-        hipLaunchKernelGGL(k_small_gemm<true>, dim3((unsigned)ceil_div(kb, 32), (unsigned)ceil_div(ka, 32)), dim3(256), 0,
-                           st, Q, ldq, Cf, (int64_t)kb, C, (int64_t)kb, ka, kb, kr);
-        CD_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div((int64_t)kb * kb, 256)), dim3(256), 0, st,
-                       Cf + (int64_t)kr * kb, (int64_t)kb, C + (int64_t)ka * kb, (int64_t)kb, kb, kb);
+    hipLaunchKernelGGL(k_small_gemm<true>, dim3((unsigned)ceil_div(kb, 32), (unsigned)ceil_div(ka + kb, 32)), dim3(256),
+                       0, st, Q, ldq, Cf, (int64_t)kb, C, (int64_t)kb, ka, kb, kr, Cf + (int64_t)kr * kb, (int64_t)kb,
+                       kb);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
@@ -264,17 +257,10 @@ chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr,
 // Qn(kr + t, :) = Y(ka + t, 0:nc) (t < kb).
 chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
                             int nc, double *Qn, int64_t ldn, hipStream_t st) {
-    if (nc == 0) return CHEBDAV_OK;
-    if (kr > 0) {
-        hipLaunchKernelGGL(k_small_gemm<false>, dim3((unsigned)ceil_div(nc, 32), (unsigned)ceil_div(kr, 32)), dim3(256), 0,
-                           st, Q, ldq, Y, ldy, Qn, ldn, kr, nc, ka);
-        CD_LAUNCH_CHECK();
-    }
-    if (kb > 0) {
-        hipLaunchKernelGGL(k_copy_rows, dim3((unsigned)ceil_div((int64_t)kb * nc, 256)), dim3(256), 0, st,
-                           Y + (int64_t)ka * ldy, ldy, Qn + (int64_t)kr * ldn, ldn, kb, nc);
-        CD_LAUNCH_CHECK();
-    }
+    if (nc == 0 || kr + kb == 0) return CHEBDAV_OK;
+    hipLaunchKernelGGL(k_small_gemm<false>, dim3((unsigned)ceil_div(nc, 32), (unsigned)ceil_div(kr + kb, 32)),
+                       dim3(256), 0, st, Q, ldq, Y, ldy, Qn, ldn, kr, nc, ka, Y + (int64_t)ka * ldy, ldy, kb);
+    CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
 

@@ -56,14 +56,18 @@ __device__ inline void load_vec(const T *p, T (&v)[VE]) {
 }
 
 // Neighbour chunk: CH column indices per group per round (each lane of the group
-// holds CH/G of them); all CH neighbour rows of a chunk are requested before any
-// is consumed, the next chunk's indices are requested before this chunk's rows,
-// and the row's own U and Z entries are requested before the neighbour loop.
-template <int G>
+// holds CH/G of them); the chunk's neighbour rows are requested UNR at a time, all
+// UNR before any of them is consumed, the next chunk's indices are requested
+// before this chunk's rows, and the row's own U and Z entries are requested
+// before the neighbour loop.
+// DEEP: 16 neighbour rows in flight per batch instead of 8 (fewer waves fit,
+// more requests each): faster when the gathered block lives in HBM, slower when
+// it fits in the caches.
+template <int G, bool DEEP>
 struct Chunk {
     static constexpr int CH = G >= 16 ? G : 16;
     static constexpr int PER = CH / G;
-    static constexpr int UNR = CH < 8 ? CH : 8;
+    static constexpr int UNR = CH < (DEEP ? 16 : 8) ? CH : (DEEP ? 16 : 8);
 };
 
 // NBR = true: the neighbour rows are scaled by their dinv (the plain product),
@@ -71,7 +75,7 @@ struct Chunk {
 // NBR = false: the block is already scaled by s = dinv (1 on isolated rows), so
 // the neighbour rows are summed as they are and the row sum takes dinv_i^2.
 // flags (kStep*): the output times s_i or divided by s_i, Z times s_i.
-template <typename T, typename TO, int VE, int G, bool NBR>
+template <typename T, typename TO, int VE, int G, bool NBR, bool DEEP>
 __global__ void __launch_bounds__(kBlock)
     k_cheb_step(int64_t n, const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
                 const double *__restrict__ nval, const T *__restrict__ dinv, T alpha, T beta, T gamma,
@@ -79,7 +83,7 @@ __global__ void __launch_bounds__(kBlock)
                 int64_t ldu, const T *__restrict__ Z, int64_t ldz, TO *__restrict__ Y, int64_t ldy,
                 int w, XcdRanges xr, int flags) {
     constexpr int GPB = kBlock / G;  // rows per block
-    constexpr int CH = Chunk<G>::CH, PER = Chunk<G>::PER, UNR = Chunk<G>::UNR;
+    constexpr int CH = Chunk<G, DEEP>::CH, PER = Chunk<G, DEEP>::PER, UNR = Chunk<G, DEEP>::UNR;
     const int lane = lane_id();
     const int gl = lane & (G - 1);
     // XCD-aware mapping: consecutive hardware block ids alternate over the eight
@@ -191,21 +195,35 @@ chebdav_status launch_ve(const Graph *g, const T *dinv, T a, T b, T c, const T *
     const int64_t grid = std::max<int64_t>(1, ceil_div(most, rows_per_block)) * kXcds;
     if (grid > INT32_MAX) return fail(CHEBDAV_EUNSUPPORTED, "grid too large");
     const dim3 gr((unsigned)grid), bl(kBlock);
-#define CD_CASE(GG)                                                                                 \
-    case GG:                                                                                        \
-        hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG, NBR>), gr, bl, 0, st, g->n, g->row_ptr, g->col, \
-                           g->nval, dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr, flags);           \
+    // deeper batches once the gathered block is larger than the 256 MB Infinity
+    // Cache (measured: 4 % faster on an 8M-node graph, 11 % slower at 200k nodes)
+    const bool deep = G >= 8 && (double)g->n * w * sizeof(T) > 256.0 * 1024 * 1024;
+#define CD_CASE(GG, DP)                                                                                 \
+    case GG:                                                                                            \
+        hipLaunchKernelGGL((k_cheb_step<T, TO, VE, GG, NBR, DP>), gr, bl, 0, st, g->n, g->row_ptr, g->col, \
+                           g->nval, dinv, a, b, c, U, ldu, Z, ldz, Y, ldy, w, xr, flags);               \
         break;
-    switch (G) {
-        CD_CASE(1)
-        CD_CASE(2)
-        CD_CASE(4)
-        CD_CASE(8)
-        CD_CASE(16)
-        CD_CASE(32)
-        CD_CASE(64)
-        default:
-            return fail(CHEBDAV_EUNSUPPORTED, "panel too wide");
+    if (deep) {
+        switch (G) {
+            CD_CASE(8, true)
+            CD_CASE(16, true)
+            CD_CASE(32, true)
+            CD_CASE(64, true)
+            default:
+                return fail(CHEBDAV_EUNSUPPORTED, "panel too wide");
+        }
+    } else {
+        switch (G) {
+            CD_CASE(1, false)
+            CD_CASE(2, false)
+            CD_CASE(4, false)
+            CD_CASE(8, false)
+            CD_CASE(16, false)
+            CD_CASE(32, false)
+            CD_CASE(64, false)
+            default:
+                return fail(CHEBDAV_EUNSUPPORTED, "panel too wide");
+        }
     }
 #undef CD_CASE
     CD_LAUNCH_CHECK();
