@@ -251,17 +251,24 @@ __global__ void __launch_bounds__(NT) k_colnorm(const double *__restrict__ X, in
 constexpr int kColnormBlocks = 1024;
 
 // One wavefront per row: stage the row's selected entries, then write them.
+__device__ inline double row_scale(const double *rs, int64_t r) {
+    if (!rs) return 1.0;
+    const double d = rs[r];
+    return d > 0.0 ? d : 1.0;
+}
+
 template <int PER_LANE>
 __global__ void k_gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
-                              const int32_t *__restrict__ map, int w, int64_t n) {
+                              const int32_t *__restrict__ map, int w, int64_t n, const double *__restrict__ rs) {
     const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
     if (r >= n) return;
     const int lane = lane_id();
+    const double sr = row_scale(rs, r);
     double v[PER_LANE];
 #pragma unroll
     for (int t = 0; t < PER_LANE; ++t) {
         const int j = lane + t * kWave;
-        v[t] = j < w ? Src[r * lds + map[j]] : 0.0;
+        v[t] = j < w ? sr * Src[r * lds + map[j]] : 0.0;
     }
 #pragma unroll
     for (int t = 0; t < PER_LANE; ++t) {
@@ -272,13 +279,13 @@ __global__ void k_gather_cols(const double *Src, int64_t lds, double *Dst, int64
 
 template <typename TS, typename TD>
 __global__ void k_copy_block(const TS *__restrict__ S, int64_t lds, TD *__restrict__ D, int64_t ldd,
-                             int w, int64_t n) {
+                             int w, int64_t n, const double *__restrict__ rs) {
     const int64_t total = n * (int64_t)w;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
         const int64_t r = e / w;
         const int c = (int)(e - r * w);
-        D[r * ldd + c] = (TD)S[r * lds + c];
+        D[r * ldd + c] = rs ? (TD)(row_scale(rs, r) * (double)S[r * lds + c]) : (TD)S[r * lds + c];
     }
 }
 
@@ -288,7 +295,7 @@ __global__ void k_fill(double *__restrict__ p, int64_t count, double v) {
 }
 
 __global__ void k_philox(double *__restrict__ X, int64_t n, int w, int64_t ld, uint64_t seed,
-                         uint64_t first_col) {
+                         uint64_t first_col, const double *__restrict__ rs) {
     const int64_t total = n * (int64_t)w;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
@@ -298,7 +305,8 @@ __global__ void k_philox(double *__restrict__ X, int64_t n, int w, int64_t ld, u
         uint32_t c[4] = {(uint32_t)r, (uint32_t)((uint64_t)r >> 32), (uint32_t)q, 0u};
         philox4x32_10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
         const uint64_t u = (((uint64_t)c[1] << 32) | c[0]) >> 11;
-        X[r * ld + j] = (double)u * 0x1.0p-52 - 1.0;
+        const double x = (double)u * 0x1.0p-52 - 1.0;
+        X[r * ld + j] = rs ? row_scale(rs, r) * x : x;
     }
 }
 
@@ -402,17 +410,17 @@ chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t l
 }
 
 chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
-                           const int32_t *map, int w, int64_t n, hipStream_t st) {
+                           const int32_t *map, int w, int64_t n, hipStream_t st, const double *rs) {
     if (w == 0 || n == 0) return CHEBDAV_OK;
     const unsigned grid = (unsigned)ceil_div(n, 4);
     if (w <= 64)
-        hipLaunchKernelGGL(k_gather_cols<1>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+        hipLaunchKernelGGL(k_gather_cols<1>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
     else if (w <= 128)
-        hipLaunchKernelGGL(k_gather_cols<2>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+        hipLaunchKernelGGL(k_gather_cols<2>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
     else if (w <= 256)
-        hipLaunchKernelGGL(k_gather_cols<4>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+        hipLaunchKernelGGL(k_gather_cols<4>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
     else if (w <= 512)
-        hipLaunchKernelGGL(k_gather_cols<8>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n);
+        hipLaunchKernelGGL(k_gather_cols<8>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
     else
         return fail(CHEBDAV_EUNSUPPORTED, "gather of more than 512 columns");
     CD_LAUNCH_CHECK();
@@ -421,19 +429,19 @@ chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t 
 
 template <typename TS, typename TD>
 chebdav_status copy_block(const TS *Src, int64_t lds, TD *Dst, int64_t ldd, int w, int64_t n,
-                          hipStream_t st) {
+                          hipStream_t st, const double *rs) {
     if (w == 0 || n == 0) return CHEBDAV_OK;
     hipLaunchKernelGGL((k_copy_block<TS, TD>), dim3(grid_for(n * w)), dim3(256), 0, st, Src, lds, Dst,
-                       ldd, w, n);
+                       ldd, w, n, rs);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
 template chebdav_status copy_block<double, double>(const double *, int64_t, double *, int64_t, int,
-                                                   int64_t, hipStream_t);
+                                                   int64_t, hipStream_t, const double *);
 template chebdav_status copy_block<double, float>(const double *, int64_t, float *, int64_t, int,
-                                                  int64_t, hipStream_t);
+                                                  int64_t, hipStream_t, const double *);
 template chebdav_status copy_block<float, double>(const float *, int64_t, double *, int64_t, int,
-                                                  int64_t, hipStream_t);
+                                                  int64_t, hipStream_t, const double *);
 
 chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st) {
     if (count == 0) return CHEBDAV_OK;
@@ -443,9 +451,9 @@ chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st) {
 }
 
 chebdav_status philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
-                           uint64_t first_col, hipStream_t st) {
+                           uint64_t first_col, hipStream_t st, const double *rs) {
     if (w == 0 || n == 0) return CHEBDAV_OK;
-    hipLaunchKernelGGL(k_philox, dim3(grid_for(n * w)), dim3(256), 0, st, X, n, w, ld, seed, first_col);
+    hipLaunchKernelGGL(k_philox, dim3(grid_for(n * w)), dim3(256), 0, st, X, n, w, ld, seed, first_col, rs);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }

@@ -95,12 +95,14 @@ chebdav_status launch_cheb_step(const Graph *g, double alpha, double beta, doubl
                                 const T *U, int64_t ldu, const T *Z, int64_t ldz, TO *Y,
                                 int64_t ldy, int w, hipStream_t st, int flags = 0);
 
-// Filter driver (Alg. 3); workspace laid out by filter_layout.
+// Filter driver (Alg. 3); workspace laid out by filter_layout.  x_scaled: X holds
+// s .* X0 (s = dinv, 1 on isolated rows) for the block X0 to be filtered; Y is
+// always the filtered X0 itself.
 size_t filter_ws_bytes(int64_t n, int kb, chebdav_dtype dt);
 chebdav_status run_filter(const Graph *g, const double *X, int64_t ldx, double *Y, int64_t ldy,
                           int kb, int m, double cut, double upper, double scale_pt,
                           chebdav_dtype dt, void *ws, size_t ws_bytes, hipStream_t st,
-                          hipEvent_t ev_begin, hipEvent_t ev_end);
+                          hipEvent_t ev_begin, hipEvent_t ev_end, bool x_scaled = false);
 
 // ---- dense.hip
 // A column-segmented tall matrix: columns [0, p1) from X1 (ld1), [p1, p1+p2) from X2 (ld2).
@@ -132,19 +134,21 @@ chebdav_status colnorms(const double *X, int64_t ldx, const double *Y, int64_t l
                         const double *theta, int w, int64_t n, double *out, double *partial,
                         hipStream_t st);
 
+// Row scaling applied by the block producers below when rs is not null: row r is
+// multiplied by rs[r], or by 1 where rs[r] is 0 (s = dinv with 1 on isolated rows).
 // Dst(:, j) = Src(:, map[j]) for j < w, row by row (Dst may equal Src: in-place
 // permutation/compaction is safe because each row is staged first).  map on device.
 chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
-                           const int32_t *map, int w, int64_t n, hipStream_t st);
+                           const int32_t *map, int w, int64_t n, hipStream_t st, const double *rs = nullptr);
 // Dst (n x w, ldd) = Src (n x w, lds), element type conversion allowed.
 template <typename TS, typename TD>
 chebdav_status copy_block(const TS *Src, int64_t lds, TD *Dst, int64_t ldd, int w, int64_t n,
-                          hipStream_t st);
+                          hipStream_t st, const double *rs = nullptr);
 // Fill a device array with a value.
 chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st);
 // Philox fill (see chebdav_philox_fill).
 chebdav_status philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
-                           uint64_t first_col, hipStream_t st);
+                           uint64_t first_col, hipStream_t st, const double *rs = nullptr);
 // flag[0] |= any non-finite entry in X (n x w, ld).
 chebdav_status check_finite(const double *X, int64_t ld, int w, int64_t n, int *flag,
                             hipStream_t st);

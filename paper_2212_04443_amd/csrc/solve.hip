@@ -20,7 +20,7 @@
 //   Va[2] n x act_max         active block V(:, kc+1 : ksub), double-buffered so
 //                             the rotation V <- V Y writes out of place
 //   W[2]  n x act_max         W = A V for the active block, double-buffered
-//   Vtmp  n x kb              the block to filter next
+//   Vtmp  n x kb              s .* (the block to filter next), s = dinv (1 on isolated rows)
 // V(:, 1:ksub) of the algorithm is the pair [Vl(:, 1:kc), Va(:, 1:kact)]; the
 // locked set is sorted by eigenvalue only when the result is written.
 #include <algorithm>
@@ -198,9 +198,9 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
     double low_nwb = r.low_nwb0;
     {
         const int take = std::min(kb, k_init);
-        if (take) CD_TRY((copy_block<double, double>(V_init, k_init, L.Vtmp, kb, take, n, st)));
+        if (take) CD_TRY((copy_block<double, double>(V_init, k_init, L.Vtmp, kb, take, n, st, g->dinv)));
         if (take < kb) {
-            CD_TRY(philox_fill(L.Vtmp + take, n, kb - take, kb, r.seed, next_col, st));
+            CD_TRY(philox_fill(L.Vtmp + take, n, kb - take, kb, r.seed, next_col, st, g->dinv));
             next_col += kb - take;
             S.n_random += kb - take;
         }
@@ -250,7 +250,7 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         // step 5: filter
         const chebdav_dtype fdt = use_f64_filter ? CHEBDAV_F64 : CHEBDAV_F32;
         CD_TRY(run_filter(g, L.Vtmp, kb, Xnew, am, kb, r.m, low_nwb, upperb, lowb, fdt, L.filt, L.filt_b,
-                          st, evp.b, evp.e));
+                          st, evp.b, evp.e, true));
         S.n_spmm_filter += r.m;
         if (fdt == CHEBDAV_F32) S.n_spmm_filter_f32 += r.m;
         // step 6: orthonormalize against V(:, 1:ksub), spanned by [Vl(:, 1:kcb), B]
@@ -378,16 +378,16 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             const int n_init = std::max(0, std::min(ec, k_init - ki));
             const int n_ritz = std::min(kb - ec, kact);
             const int pad = kb - n_init - n_ritz;
-            if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, L.Vtmp, kb, n_init, n, st)));
+            if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, L.Vtmp, kb, n_init, n, st, g->dinv)));
             if (n_ritz) {
                 // the leading non-converged pairs are all among the first nres columns of PV
                 if (ec)
-                    CD_TRY(gather_cols(PV, ldp, L.Vtmp + n_init, kb, L.map + am, n_ritz, n, st));
+                    CD_TRY(gather_cols(PV, ldp, L.Vtmp + n_init, kb, L.map + am, n_ritz, n, st, g->dinv));
                 else
-                    CD_TRY((copy_block<double, double>(PV, ldp, L.Vtmp + n_init, kb, n_ritz, n, st)));
+                    CD_TRY((copy_block<double, double>(PV, ldp, L.Vtmp + n_init, kb, n_ritz, n, st, g->dinv)));
             }
             if (pad) {
-                CD_TRY(philox_fill(L.Vtmp + n_init + n_ritz, n, pad, kb, r.seed, next_col, st));
+                CD_TRY(philox_fill(L.Vtmp + n_init + n_ritz, n, pad, kb, r.seed, next_col, st, g->dinv));
                 next_col += pad;
                 S.n_random += pad;
             }

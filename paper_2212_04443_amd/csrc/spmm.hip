@@ -308,7 +308,7 @@ namespace {
 template <typename T>
 chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y, int64_t ldy,
                            int kb, int m, double cut, double upper, double scale_pt, T *bufs[3],
-                           hipStream_t st) {
+                           hipStream_t st, bool x_scaled) {
     const double e = (upper - cut) / 2.0;
     const double c = (upper + cut) / 2.0;
     double sigma = e / (scale_pt - c);
@@ -317,13 +317,16 @@ chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y,
     // The work blocks hold s .* U_k (s = dinv, 1 on isolated rows): A = I - diag(s)
     // S diag(s), so s .* (A U) = s .* U - s^2 .* (S (s .* U)) and the steps after the
     // first gather unscaled rows (no per-neighbour dinv).  The first step scales
-    // its output, the second scales its Z = X, the last divides its output by s.
+    // its output, the second scales its Z = X, the last divides its output by s;
+    // with x_scaled (x0 = s .* X) the first two are steps like the others.
     // step 1
     {
         const double al = -sigma / e, be = sigma * (1.0 - c) / e;
         if (m == 1)
-            return launch_cheb_step<T, double>(g, al, be, 0.0, x0, ldx0, nullptr, 0, Y, ldy, kb, st);
-        CD_TRY((launch_cheb_step<T, T>(g, al, be, 0.0, x0, ldx0, nullptr, 0, bufs[0], ldb, kb, st, kStepOutMulS)));
+            return launch_cheb_step<T, double>(g, al, be, 0.0, x0, ldx0, nullptr, 0, Y, ldy, kb, st,
+                                               x_scaled ? (kStepScaled | kStepOutDivS) : 0);
+        CD_TRY((launch_cheb_step<T, T>(g, al, be, 0.0, x0, ldx0, nullptr, 0, bufs[0], ldb, kb, st,
+                                       x_scaled ? kStepScaled : kStepOutMulS)));
     }
     const T *prev = x0;
     int64_t ldp = ldx0;
@@ -333,7 +336,7 @@ chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y,
         const double al = -2.0 * sigma1 / e;
         const double be = 2.0 * sigma1 * (1.0 - c) / e;
         const double ga = -sigma * sigma1;
-        const int fl = kStepScaled | (k == 2 ? kStepZMulS : 0);
+        const int fl = kStepScaled | (k == 2 && !x_scaled ? kStepZMulS : 0);
         if (k == m) {
             CD_TRY((launch_cheb_step<T, double>(g, al, be, ga, cur, ldb, prev, ldp, Y, ldy, kb, st, fl | kStepOutDivS)));
         } else {
@@ -352,7 +355,7 @@ chebdav_status filter_impl(const Graph *g, const T *x0, int64_t ldx0, double *Y,
 chebdav_status run_filter(const Graph *g, const double *X, int64_t ldx, double *Y, int64_t ldy,
                           int kb, int m, double cut, double upper, double scale_pt,
                           chebdav_dtype dt, void *ws, size_t ws_bytes, hipStream_t st,
-                          hipEvent_t ev_begin, hipEvent_t ev_end) {
+                          hipEvent_t ev_begin, hipEvent_t ev_end, bool x_scaled) {
     if (m < 1 || kb < 1) return fail(CHEBDAV_EINVAL, "need m >= 1 and kb >= 1");
     if (!(scale_pt < cut && cut < upper)) return fail(CHEBDAV_EINVAL, "need scale_pt < cut < upper");
     if (ldx < kb || ldy < kb) return fail(CHEBDAV_EINVAL, "leading dimension < kb");
@@ -366,13 +369,13 @@ chebdav_status run_filter(const Graph *g, const double *X, int64_t ldx, double *
     if (dt == CHEBDAV_F64) {
         double *b[3] = {reinterpret_cast<double *>(w), reinterpret_cast<double *>(w + blk),
                         reinterpret_cast<double *>(w + 2 * blk)};
-        CD_TRY(filter_impl<double>(g, X, ldx, Y, ldy, kb, m, cut, upper, scale_pt, b, st));
+        CD_TRY(filter_impl<double>(g, X, ldx, Y, ldy, kb, m, cut, upper, scale_pt, b, st, x_scaled));
     } else {
         float *x32 = reinterpret_cast<float *>(w + 3 * blk);
         CD_TRY((copy_block<double, float>(X, ldx, x32, kb, kb, g->n, st)));
         float *b[3] = {reinterpret_cast<float *>(w), reinterpret_cast<float *>(w + blk),
                        reinterpret_cast<float *>(w + 2 * blk)};
-        CD_TRY(filter_impl<float>(g, x32, kb, Y, ldy, kb, m, cut, upper, scale_pt, b, st));
+        CD_TRY(filter_impl<float>(g, x32, kb, Y, ldy, kb, m, cut, upper, scale_pt, b, st, x_scaled));
     }
     if (ev_end) CD_HIP(hipEventRecord(ev_end, st));
     return CHEBDAV_OK;
