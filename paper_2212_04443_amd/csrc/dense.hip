@@ -146,76 +146,119 @@ int gram_splits(int64_t n, int p, int q) {
     return (int)s;
 }
 
-// Y = alpha Xs B + beta Y on matrix cores: one wavefront owns a 64-row x
-// (16 TQT)-column tile of Y, accumulates over all p columns of Xs (four per MFMA
-// step; lane k*16 + i reads row i, column k: consecutive lanes of a row read
-// adjacent elements; 4 UR columns per loop trip, the next trip's loads issued
-// before the current trip's MFMAs) and writes the tile only at the end, so Y
-// may alias Xs when it has a single column tile.
-template <int TQT, int UR>
-__global__ void __launch_bounds__(64) k_update(Seg2 xs, const double *__restrict__ B, int64_t ldb,
-                                               double alpha, double beta, double *Y, int64_t ldy, int q,
-                                               int64_t n) {
-    const int p = xs.cols();
-    const int lane = threadIdx.x;
+// Y = alpha Xs B + beta Y on matrix cores.  A block of NW wavefronts covers
+// 16 TR NW consecutive rows and (16 TQT) columns of Y; each wavefront owns 16 TR
+// rows, accumulates over all p columns of Xs and writes its tile only at the
+// end, so Y may alias Xs when it has a single column tile.  The reduction index
+// runs over 16-column groups of the two segments of Xs (a segment's last group
+// is zero-padded), and inside a group it is permuted per lane: lane group kr
+// takes columns 2kr, 2kr + 1 and 8 + 2kr, 9 + 2kr, so one 16-byte load per
+// lane covers a contiguous 64-byte half of every row's 128-byte group (two
+// 8-byte loads when the segment's base or leading dimension is not 16-byte
+// aligned).  The rows of B for 64 such indices at a time are staged in LDS,
+// shared by the block's wavefronts, and the X loads of the next group are issued
+// before the MFMAs of the current one.  Fewer registers per wavefront (B is not
+// held in registers) keep 4-8 wavefronts per SIMD resident.
+typedef double d2_t __attribute__((ext_vector_type(2)));
+
+template <int TR, int TQT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_update(Seg2 xs, int vec1, int vec2, const double *__restrict__ B,
+                                                    int64_t ldb, double alpha, double beta, double *Y, int64_t ldy,
+                                                    int q, int64_t n) {
+    constexpr int QW = 16 * TQT, KC = 64;
+    __shared__ double sB[KC * QW];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kr = lane >> 4, cc = lane & 15;
-    const int64_t r0 = (int64_t)blockIdx.x * 64;
-    const int j0 = blockIdx.y * (16 * TQT);
-    d4_t acc[4][TQT];
+    const int64_t r0 = ((int64_t)blockIdx.x * NW + wave) * 16 * TR;
+    const int j0 = blockIdx.y * QW;
+    const int g1 = (xs.p1 + 15) >> 4;                // 16-column groups of segment 1
+    const int pv = 16 * (g1 + ((xs.p2 + 15) >> 4));  // padded reduction length
+    d4_t acc[TR][TQT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TR; ++t)
 #pragma unroll
         for (int u = 0; u < TQT; ++u) acc[t][u] = d4_t{0.0, 0.0, 0.0, 0.0};
-    bool rowv[4], colw[TQT];
+    bool rowv[TR];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) rowv[t] = r0 + 16 * t + cc < n;
+    for (int t = 0; t < TR; ++t) rowv[t] = r0 + 16 * t + cc < n;
+    // X(row, v .. v+15) for this lane's two column pairs of group v / 16
+    auto xload = [&](int v, d2_t (&a)[TR][2]) {
+        const bool s1 = v < 16 * g1;
+        const double *base = s1 ? xs.X1 : xs.X2;
+        const int64_t ld = s1 ? xs.ld1 : xs.ld2;
+        const int pc = s1 ? xs.p1 : xs.p2;
+        const int cb = s1 ? v : v - 16 * g1;
+        const bool vec = s1 ? vec1 : vec2;
 #pragma unroll
-    for (int u = 0; u < TQT; ++u) colw[u] = j0 + 16 * u + cc < q;
-    auto load = [&](int k0, double (&a)[UR][4], double (&b)[UR][TQT]) {
+        for (int h = 0; h < 2; ++h) {
+            const int c = cb + 8 * h + 2 * kr;
 #pragma unroll
-        for (int h = 0; h < UR; ++h) {
-            const int kk = k0 + 4 * h + kr;
-            const bool kv = kk < p;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) a[h][t] = (kv && rowv[t]) ? seg_load(xs, r0 + 16 * t + cc, kk) : 0.0;
-#pragma unroll
-            for (int u = 0; u < TQT; ++u) b[h][u] = (kv && colw[u]) ? B[(int64_t)kk * ldb + j0 + 16 * u + cc] : 0.0;
+            for (int t = 0; t < TR; ++t) {
+                const double *src = base + (r0 + 16 * t + cc) * ld + c;
+                d2_t x = d2_t{0.0, 0.0};
+                if (rowv[t] && c + 1 < pc) {
+                    if (vec)
+                        x = *reinterpret_cast<const d2_t *>(src);
+                    else
+                        x = d2_t{src[0], src[1]};
+                } else if (rowv[t] && c < pc) {
+                    x.x = src[0];
+                }
+                a[t][h] = x;
+            }
         }
     };
-    auto trip = [&](double (&a)[UR][4], double (&b)[UR][TQT]) {
+    // MFMA step s of a group uses reduction index 8 (s >> 1) + 2 kr + (s & 1)
+    auto trip = [&](int v, d2_t (&a)[TR][2]) {
+        double b[4][TQT];
 #pragma unroll
-        for (int h = 0; h < UR; ++h)
+        for (int s = 0; s < 4; ++s) {
+            const int e = (v % KC) + 8 * (s >> 1) + 2 * kr + (s & 1);
 #pragma unroll
-            for (int t = 0; t < 4; ++t)
+            for (int u = 0; u < TQT; ++u) b[s][u] = sB[e * QW + 16 * u + cc];
+        }
 #pragma unroll
-                for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int t = 0; t < TR; ++t)
+#pragma unroll
+                for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[t][s >> 1][s & 1], b[s][u], acc[t][u]);
     };
-    constexpr int step = 4 * UR;
-    double a0[UR][4], b0[UR][TQT], a1[UR][4], b1[UR][TQT];
-    int k0 = 0;
-    load(0, a0, b0);
-    while (k0 < p) {
-        const int k1 = k0 + step;
-        if (k1 < p) load(k1, a1, b1);
-        trip(a0, b0);
-        if (k1 >= p) break;
-        const int k2 = k1 + step;
-        if (k2 < p) load(k2, a0, b0);
-        trip(a1, b1);
-        k0 = k2;
+    d2_t a0[TR][2], a1[TR][2];
+    if (pv > 0) xload(0, a0);
+    for (int v0 = 0; v0 < pv; v0 += KC) {
+        __syncthreads();  // every wavefront is done with the previous chunk
+        for (int e = threadIdx.x; e < KC * QW; e += 64 * NW) {
+            const int v = v0 + e / QW, j = j0 + e % QW;
+            const bool s1 = v < 16 * g1;
+            const int c = s1 ? v : v - 16 * g1;
+            const bool ok = j < q && (s1 ? c < xs.p1 : (v < pv && c < xs.p2));
+            sB[e] = ok ? B[(int64_t)(s1 ? c : xs.p1 + c) * ldb + j] : 0.0;
+        }
+        __syncthreads();
+        // a chunk holds 4 groups (fewer only in the last chunk), so every chunk
+        // but the last starts with its first group in a0
+        const int vend = min(pv, v0 + KC);
+        for (int v = v0; v < vend; v += 32) {
+            if (v + 16 < pv) xload(v + 16, a1);
+            trip(v, a0);
+            if (v + 16 >= vend) break;
+            if (v + 32 < pv) xload(v + 32, a0);
+            trip(v + 16, a1);
+        }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TR; ++t)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int64_t row = r0 + 16 * t + kr + 4 * v;
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = r0 + 16 * t + kr + 4 * r;
             if (row >= n) continue;
 #pragma unroll
             for (int u = 0; u < TQT; ++u) {
                 const int j = j0 + 16 * u + cc;
                 if (j >= q) continue;
                 double *y = Y + row * ldy + j;
-                *y = beta == 0.0 ? alpha * acc[t][u][v] : alpha * acc[t][u][v] + beta * (*y);
+                *y = beta == 0.0 ? alpha * acc[t][u][r] : alpha * acc[t][u][r] + beta * (*y);
             }
         }
 }
@@ -377,14 +420,24 @@ chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha
         if (beta == 1.0) return CHEBDAV_OK;
         return fail(CHEBDAV_EUNSUPPORTED, "update with an empty basis");
     }
+    auto vec_ok = [](const double *X, int64_t ld) {
+        return (reinterpret_cast<uintptr_t>(X) % 16) == 0 && ld % 2 == 0;
+    };
+    const int vec1 = Xs.p1 > 0 && vec_ok(Xs.X1, Xs.ld1);
+    const int vec2 = Xs.p2 > 0 && vec_ok(Xs.X2, Xs.ld2);
     const int qt = std::min(q, TB);
-    const dim3 grid((unsigned)ceil_div(n, TB), (unsigned)ceil_div(q, qt));
-    if (qt <= 16)
-        hipLaunchKernelGGL((k_update<1, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    else if (qt <= 32)
-        hipLaunchKernelGGL((k_update<2, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
-    else
-        hipLaunchKernelGGL((k_update<4, 2>), grid, dim3(64), 0, st, Xs, B, ldb, alpha, beta, Y, ldy, q, n);
+    const unsigned gy = (unsigned)ceil_div(q, qt);
+    // rows per block: 16 TR NW (measured best: TR = 1 up to 32 columns, TR = 2 for 64; NW = 8)
+    if (qt <= 16) {
+        const dim3 grid((unsigned)ceil_div(n, 256), gy);
+        hipLaunchKernelGGL((k_update<2, 1, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+    } else if (qt <= 32) {
+        const dim3 grid((unsigned)ceil_div(n, 128), gy);
+        hipLaunchKernelGGL((k_update<1, 2, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+    } else {
+        const dim3 grid((unsigned)ceil_div(n, 256), gy);
+        hipLaunchKernelGGL((k_update<2, 4, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+    }
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
