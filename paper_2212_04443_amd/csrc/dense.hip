@@ -106,7 +106,10 @@ __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__
 // consecutive elements; thread group zg (ZG groups) adds splits z = zg, zg + ZG,
 // ... into four accumulators (z mod 4 ZG), combined as (a0 + a1) + (a2 + a3);
 // the ZG group sums are then added in order.  The order depends only on S.
-// MODE 0 writes C[(e / q) * ldc + e % q] (a Gram tile); MODE 1 writes sqrt(sum) to C[e].
+// MODE 0 writes C[(e / q) * ldc + e % q] (a Gram tile); MODE 1 writes sqrt(sum) to C[e];
+// MODE 2 (square Gram G = X^T X) writes the Newton-Schulz matrix (3 I - G) / 2 in
+// the layout of MODE 0 (one step X <- X (3 I - X^T X) / 2 towards the
+// orthonormal polar factor when X^T X is close to I).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part, int S, int64_t E, int q,
                                                 double *__restrict__ C, int64_t ldc) {
@@ -133,8 +136,10 @@ __global__ void __launch_bounds__(256) k_reduce(const double *__restrict__ part,
         for (int g = 0; g < ZG; ++g) t += sh[g][el];
         if (MODE == 0)
             C[(e / q) * ldc + (e % q)] = t;
-        else
+        else if (MODE == 1)
             C[e] = sqrt(t);
+        else
+            C[(e / q) * ldc + (e % q)] = ((e / q) == (e % q) ? 1.5 : 0.0) - 0.5 * t;
     }
 }
 
@@ -300,6 +305,24 @@ __device__ inline double row_scale(const double *rs, int64_t r) {
     return d > 0.0 ? d : 1.0;
 }
 
+// Up to 64 columns: a wavefront holds 64 / wp rows (wp = w rounded up to a power
+// of two), thread (row slot, column c) loads map[c] once and walks the rows with a
+// grid stride.  A row never spans two wavefronts, and every lane of a wavefront
+// issues its load before any lane stores, so Src may alias Dst.
+__global__ void k_gather_cols_packed(const double *Src, int64_t lds, double *Dst, int64_t ldd,
+                                     const int32_t *__restrict__ map, int w, int wp_log2, int64_t n,
+                                     const double *__restrict__ rs) {
+    const int c = threadIdx.x & ((1 << wp_log2) - 1);
+    const int slot = threadIdx.x >> wp_log2;
+    const int rows_per_block = blockDim.x >> wp_log2;
+    const bool active = c < w;
+    const int src_c = active ? map[c] : 0;
+    for (int64_t r = (int64_t)blockIdx.x * rows_per_block + slot; r < n; r += (int64_t)gridDim.x * rows_per_block) {
+        const double v = active ? row_scale(rs, r) * Src[r * lds + src_c] : 0.0;
+        if (active) Dst[r * ldd + c] = v;
+    }
+}
+
 template <int PER_LANE>
 __global__ void k_gather_cols(const double *Src, int64_t lds, double *Dst, int64_t ldd,
                               const int32_t *__restrict__ map, int w, int64_t n, const double *__restrict__ rs) {
@@ -380,7 +403,7 @@ size_t gram_partial_elems(int64_t, int p, int q) {
 }
 
 chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t n, double *C,
-                    int64_t ldc, double *partial, hipStream_t st) {
+                    int64_t ldc, double *partial, hipStream_t st, bool ns) {
     const int p = Xs.cols();
     if (p == 0 || q == 0) return CHEBDAV_OK;
     const int splits = gram_splits(n, p, q);
@@ -405,8 +428,13 @@ chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t
     }
     CD_LAUNCH_CHECK();
     const int64_t pq = (int64_t)p * q;
-    hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 8)), dim3(256), 0, st, partial, splits, pq,
-                       q, C, ldc);
+    if (ns && p != q) return fail(CHEBDAV_EINVAL, "Newton-Schulz matrix of a non-square Gram product");
+    if (ns)
+        hipLaunchKernelGGL(k_reduce<2>, dim3((unsigned)ceil_div(pq, 8)), dim3(256), 0, st, partial, splits, pq,
+                           q, C, ldc);
+    else
+        hipLaunchKernelGGL(k_reduce<0>, dim3((unsigned)ceil_div(pq, 8)), dim3(256), 0, st, partial, splits, pq,
+                           q, C, ldc);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
@@ -466,9 +494,13 @@ chebdav_status gather_cols(const double *Src, int64_t lds, double *Dst, int64_t 
                            const int32_t *map, int w, int64_t n, hipStream_t st, const double *rs) {
     if (w == 0 || n == 0) return CHEBDAV_OK;
     const unsigned grid = (unsigned)ceil_div(n, 4);
-    if (w <= 64)
-        hipLaunchKernelGGL(k_gather_cols<1>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
-    else if (w <= 128)
+    if (w <= 64) {
+        int lg = 0;
+        while ((1 << lg) < w) ++lg;
+        const int64_t rows_per_block = 256 >> lg;
+        const unsigned pg = (unsigned)std::min<int64_t>(ceil_div(n, rows_per_block), 4096);
+        hipLaunchKernelGGL(k_gather_cols_packed, dim3(pg), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, lg, n, rs);
+    } else if (w <= 128)
         hipLaunchKernelGGL(k_gather_cols<2>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);
     else if (w <= 256)
         hipLaunchKernelGGL(k_gather_cols<4>, dim3(grid), dim3(256), 0, st, Src, lds, Dst, ldd, map, w, n, rs);

@@ -730,8 +730,7 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
         stt.X1 = s.T;
         stt.ld1 = n;
         stt.p1 = n;
-        CD_TRY(gram(stt, s.T, n, n, n, s.G, n, s.part, st));
-        CD_TRY(ns_matrix(s.G, n, s.Bm, st));
+        CD_TRY(gram(stt, s.T, n, n, n, s.Bm, n, s.part, st, true));
         CD_TRY(update(stt, s.Bm, n, 1.0, 0.0, Y, ldy, n, n, st));
     }
     hipLaunchKernelGGL(k_copy_vec, dim3(g64), dim3(64), 0, st, s.w, evals, n);

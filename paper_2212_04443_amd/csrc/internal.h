@@ -118,9 +118,11 @@ struct Seg2 {
 
 // C (p x q, row-major, ldc) = Xs^T Y over n rows; Y: n x q (ldy).  Uses a
 // deterministic split over rows with partials in `partial` (gram_partial_elems).
+// With ns = true (p == q, Y = Xs) C receives (3 I - Xs^T Xs) / 2 instead: the
+// matrix of one Newton-Schulz orthonormalization step X <- X C.
 size_t gram_partial_elems(int64_t n, int p, int q);
 chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t n, double *C,
-                    int64_t ldc, double *partial, hipStream_t st);
+                    int64_t ldc, double *partial, hipStream_t st, bool ns = false);
 
 // Y (n x q, ldy) = alpha * Xs B + beta * Y, with B (p x q, row-major, ldb).  Y may
 // alias a column block of Xs only when q <= update_max_inplace_cols().
@@ -168,8 +170,6 @@ chebdav_status h_set_diag(double *H, int64_t ldh, const double *d, int k, hipStr
 // Q <- [[Q, 0], [0, I]] Y.
 chebdav_status proj_cols(const double *Q, int64_t ldq, const double *Cf, int kr, int ka, int kb, double *C,
                          hipStream_t st);
-// B = (3 I - G) / 2 (n x n, contiguous): one Newton-Schulz orthonormalization step.
-chebdav_status ns_matrix(const double *G, int n, double *B, hipStream_t st);
 chebdav_status extend_basis(const double *Q, int64_t ldq, const double *Y, int64_t ldy, int kr, int ka, int kb,
                             int nc, double *Qn, int64_t ldn, hipStream_t st);
 

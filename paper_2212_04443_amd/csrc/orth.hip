@@ -163,8 +163,7 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
         CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
         CD_TRY(chol_rinv(s.G, kb, nullptr, s.Rinv, s.dep, 0, st));
     } else {
-        CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));
-        CD_TRY(ns_matrix(s.G, kb, s.Rinv, st));
+        CD_TRY(gram(xs, X, ldx, kb, n, s.Rinv, kb, s.part, st, true));
     }
     CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
     if (n_replaced) *n_replaced = replaced;

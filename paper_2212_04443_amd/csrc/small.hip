@@ -128,16 +128,6 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
     if (tid < kb) dep[tid] = d[tid];
 }
 
-// B = (3 I - G) / 2: one Newton-Schulz step X <- X B towards the orthonormal
-// polar factor of X when G = X^T X is close to I (X^T X then deviates from I by
-// O(||G - I||^2)).
-__global__ void k_ns_matrix(const double *__restrict__ G, int n, double *__restrict__ B) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)n * n) return;
-    const int i = (int)(q / n), j = (int)(q % n);
-    B[q] = (i == j ? 1.5 : 0.0) - 0.5 * G[q];
-}
-
 __global__ void k_h_insert(double *__restrict__ H, int64_t ldh, const double *__restrict__ C, int k,
                            int kb) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -213,12 +203,6 @@ chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *R
                          int scaled, hipStream_t st) {
     if (kb < 1 || kb > kMaxKb) return fail(CHEBDAV_EUNSUPPORTED, "block size %d outside [1, %d]", kb, kMaxKb);
     hipLaunchKernelGGL(k_chol_rinv, dim3(1), dim3(256), 0, st, G, kb, norm0, Rinv, dep, scaled);
-    CD_LAUNCH_CHECK();
-    return CHEBDAV_OK;
-}
-
-chebdav_status ns_matrix(const double *G, int n, double *B, hipStream_t st) {
-    hipLaunchKernelGGL(k_ns_matrix, dim3((unsigned)ceil_div((int64_t)n * n, 256)), dim3(256), 0, st, G, n, B);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }

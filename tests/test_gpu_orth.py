@@ -64,3 +64,31 @@ def test_exactly_dependent_columns(cd, oracle_mod, dev):
     # the independent columns keep their span
     keep = X[:, [0, 1, 3]] - V @ (V.T @ X[:, [0, 1, 3]])
     assert np.linalg.norm(keep - Q @ (Q.T @ keep)) <= 1e-12 * np.linalg.norm(keep)
+
+
+@pytest.mark.parametrize("n,ksub,kb,ldv,ldx,offv,offx",
+                         [(3001, 37, 33, 41, 35, 3, 1), (4099, 150, 64, 151, 66, 0, 2), (2500, 16, 17, 16, 18, 0, 1)])
+def test_strided_unaligned_views(cd, dev, n, ksub, kb, ldv, ldx, offv, offx):
+    """V and X as column windows of wider arrays (odd leading dimensions, bases
+    not 16-byte aligned): same invariants, and the columns beside the window
+    are left untouched."""
+    import torch
+    print("case orth views n=%d ksub=%d kb=%d ldv=%d ldx=%d" % (n, ksub, kb, ldv, ldx), flush=True)
+    V = _basis(n, ksub, 11)
+    X = np.random.default_rng(12).standard_normal((n, kb))
+    Vbig = np.random.default_rng(13).standard_normal((n, ldv + offv))
+    Vbig[:, offv:offv + ksub] = V
+    Xbig = np.random.default_rng(14).standard_normal((n, ldx + offx))
+    Xbig[:, offx:offx + kb] = X
+    Vb = torch.from_numpy(Vbig).cuda()
+    Xb = torch.from_numpy(Xbig).cuda()
+    rep = cd.orthonormalize(Vb[:, offv:offv + ksub], Xb[:, offx:offx + kb], seed=0)
+    out = Xb.cpu().numpy()
+    Q = out[:, offx:offx + kb]
+    assert rep == 0
+    assert np.array_equal(np.delete(out, np.s_[offx:offx + kb], axis=1), np.delete(Xbig, np.s_[offx:offx + kb], axis=1))
+    assert np.array_equal(Vb.cpu().numpy(), Vbig)
+    assert np.linalg.norm(Q.T @ Q - np.eye(kb), 2) <= 10 * kb * EPS
+    assert np.linalg.norm(V.T @ Q, 2) <= 10 * ksub * EPS
+    Xp = X - V @ (V.T @ X)
+    assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-12 * np.linalg.norm(Xp)
