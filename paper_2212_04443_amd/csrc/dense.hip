@@ -160,17 +160,18 @@ int gram_splits(int64_t n, int p, int q) {
 // takes columns 2kr, 2kr + 1 and 8 + 2kr, 9 + 2kr, so one 16-byte load per
 // lane covers a contiguous 64-byte half of every row's 128-byte group (two
 // 8-byte loads when the segment's base or leading dimension is not 16-byte
-// aligned).  The rows of B for 64 such indices at a time are staged in LDS,
+// aligned).  The rows of B for KC such indices at a time (128 up to 32 columns,
+// 64 for 64 columns: 32 KB either way) are staged in LDS,
 // shared by the block's wavefronts, and the X loads of the next group are issued
 // before the MFMAs of the current one.  Fewer registers per wavefront (B is not
 // held in registers) keep 4-8 wavefronts per SIMD resident.
 typedef double d2_t __attribute__((ext_vector_type(2)));
 
-template <int TR, int TQT, int NW>
+template <int TR, int TQT, int NW, int KC>
 __global__ void __launch_bounds__(64 * NW) k_update(Seg2 xs, int vec1, int vec2, const double *__restrict__ B,
                                                     int64_t ldb, double alpha, double beta, double *Y, int64_t ldy,
                                                     int q, int64_t n) {
-    constexpr int QW = 16 * TQT, KC = 64;
+    constexpr int QW = 16 * TQT;
     __shared__ double sB[KC * QW];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kr = lane >> 4, cc = lane & 15;
@@ -241,8 +242,8 @@ __global__ void __launch_bounds__(64 * NW) k_update(Seg2 xs, int vec1, int vec2,
             sB[e] = ok ? B[(int64_t)(s1 ? c : xs.p1 + c) * ldb + j] : 0.0;
         }
         __syncthreads();
-        // a chunk holds 4 groups (fewer only in the last chunk), so every chunk
-        // but the last starts with its first group in a0
+        // a chunk holds KC / 16 groups, an even number (fewer only in the last
+        // chunk), so every chunk but the last starts with its first group in a0
         const int vend = min(pv, v0 + KC);
         for (int v = v0; v < vend; v += 32) {
             if (v + 16 < pv) xload(v + 16, a1);
@@ -455,16 +456,17 @@ chebdav_status update(const Seg2 &Xs, const double *B, int64_t ldb, double alpha
     const int vec2 = Xs.p2 > 0 && vec_ok(Xs.X2, Xs.ld2);
     const int qt = std::min(q, TB);
     const unsigned gy = (unsigned)ceil_div(q, qt);
-    // rows per block: 16 TR NW (measured best: TR = 1 up to 32 columns, TR = 2 for 64; NW = 8)
+    // rows per block: 16 TR NW (measured best: TR = 1 up to 32 columns, TR = 2 for 64; NW = 8;
+    // KC = 128 is 2-5 % faster than 64 up to 32 columns, equal at 64)
     if (qt <= 16) {
         const dim3 grid((unsigned)ceil_div(n, 256), gy);
-        hipLaunchKernelGGL((k_update<2, 1, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+        hipLaunchKernelGGL((k_update<2, 1, 8, 128>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
     } else if (qt <= 32) {
         const dim3 grid((unsigned)ceil_div(n, 128), gy);
-        hipLaunchKernelGGL((k_update<1, 2, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+        hipLaunchKernelGGL((k_update<1, 2, 8, 128>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
     } else {
         const dim3 grid((unsigned)ceil_div(n, 256), gy);
-        hipLaunchKernelGGL((k_update<2, 4, 8>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
+        hipLaunchKernelGGL((k_update<2, 4, 8, 64>), grid, dim3(512), 0, st, Xs, vec1, vec2, B, ldb, alpha, beta, Y, ldy, q, n);
     }
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
