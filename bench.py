@@ -132,6 +132,40 @@ def lanczos_form(cd, torch, g, cfg, steps, seed, lanczos_steps=10):
     return out
 
 
+def streaming_form(cd, torch, edges, n, cfg, prev_evecs, steps, seed, frac=0.005):
+    """Streaming-graph use of V_init (Sec. 1; Alg. 2 step 2): a fraction `frac` of
+    the edges is rewired at random, and the FP64 solve of the new graph starts
+    from the eigenvectors of the old one.  Reports it beside a random start on
+    the same new graph (graph build excluded from both)."""
+    import numpy as np
+    rng = np.random.default_rng(seed + 7919)
+    keep = rng.random(len(edges)) >= frac
+    fresh = rng.integers(0, n, size=(int((~keep).sum()), 2))
+    g1 = cd.build_laplacian(np.concatenate([edges[keep], fresh]).astype(np.int64), n)
+    p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed)
+    ws = torch.empty(cd.solve_workspace_size(g1, p), dtype=torch.uint8, device="cuda")
+    V0 = prev_evecs.contiguous()
+    rec = {"rewired_fraction": frac}
+    for name, vi in (("random_start", None), ("previous_eigenvectors", V0)):
+        cd.solve(g1, p, V_init=vi, workspace=ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = cd.solve(g1, p, V_init=vi, workspace=ws)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / steps
+        rec[name] = dict(seconds=t, iterations=r.stats["iterations"], max_residual=r.stats["max_residual"])
+        rec[name + "_evals"] = r.evals.cpu().numpy()
+    rec["max_dlambda"] = float(np.abs(rec.pop("random_start_evals") - rec.pop("previous_eigenvectors_evals")).max())
+    log("streaming warm start (%.1f %% of edges rewired): random start %.2f ms, %d iterations; "
+        "previous eigenvectors %.2f ms, %d iterations" % (100 * frac, 1e3 * rec["random_start"]["seconds"],
+        rec["random_start"]["iterations"], 1e3 * rec["previous_eigenvectors"]["seconds"],
+        rec["previous_eigenvectors"]["iterations"]))
+    del ws, g1
+    torch.cuda.empty_cache()
+    return rec
+
+
 def cluster_tail(cd, evecs, truth, k, seed):
     """Clustering tail (row normalization + K-means) on the FP64 eigenvectors,
     scored against the planted blocks."""
@@ -229,6 +263,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the GCN warm-start forms")
     ap.add_argument("--no-cluster", action="store_true", help="skip the clustering tail")
     ap.add_argument("--no-lanczos", action="store_true", help="skip the form with a Lanczos upper bound")
+    ap.add_argument("--no-streaming", action="store_true",
+                    help="skip the streaming-graph warm start (rewired graph, previous eigenvectors as V_init)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -327,6 +363,9 @@ def main():
         line["f64_lanczos_upper_max_dlambda"] = float(np.abs(lf["evals"] - prim["evals"]).max())
     if "f64" in res and not args.no_cluster:
         line["cluster_tail"] = cluster_tail(cd, res["f64"]["evecs"], cfg.get("labels"), cfg["k"], args.seed)
+    if "f64" in res and not args.no_streaming:
+        line["streaming_warm_start"] = streaming_form(cd, torch, edges, n, cfg, res["f64"]["evecs"], args.steps,
+                                                      args.seed)
     if not args.no_cpu_baseline:
         log("running the CPU oracle on the same workload ...")
         cb, ref = cpu_baseline(edges, n, cfg, args.seed)
