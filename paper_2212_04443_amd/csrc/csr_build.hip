@@ -262,25 +262,35 @@ __global__ void k_dinv_table(const int32_t *__restrict__ deg, double *__restrict
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dinv[i] = dinv_of(deg[i]);
 }
 
-// Final placement + degree scaling.  One wavefront per row.
+// Final placement + degree scaling.  Each wavefront walks rows with a grid
+// stride (lanes over a row's columns) and keeps its isolated-row count and
+// largest degree in registers: one pair of atomics per wavefront, not per row
+// (200k same-address atomics serialize to milliseconds).
 __global__ void k_compact(const int64_t *__restrict__ off, const int32_t *__restrict__ ucnt,
                           const int32_t *__restrict__ buf, const int64_t *__restrict__ row_ptr,
                           int32_t *__restrict__ col, int32_t *__restrict__ deg,
                           double *__restrict__ dinv, float *__restrict__ dinv32, int64_t n,
                           int *__restrict__ stats) {
     const int lane = lane_id();
-    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (r >= n) return;
-    const int L = ucnt[r];
-    const int64_t src = off[r], dst = row_ptr[r];
-    for (int i = lane; i < L; i += kWave) col[dst + i] = buf[src + i];
+    const int64_t wpb = blockDim.x / kWave;
+    const int64_t stride = (int64_t)gridDim.x * wpb;
+    int zeros = 0, mx = 0;
+    for (int64_t r = (int64_t)blockIdx.x * wpb + threadIdx.x / kWave; r < n; r += stride) {
+        const int L = ucnt[r];
+        const int64_t src = off[r], dst = row_ptr[r];
+        for (int i = lane; i < L; i += kWave) col[dst + i] = buf[src + i];
+        if (lane == 0) {
+            deg[r] = L;
+            const double di = dinv_of(L);
+            dinv[r] = di;
+            dinv32[r] = (float)di;
+        }
+        zeros += L == 0;
+        mx = max(mx, L);
+    }
     if (lane == 0) {
-        deg[r] = L;
-        const double di = dinv_of(L);
-        dinv[r] = di;
-        dinv32[r] = (float)di;
-        if (L == 0) atomicAdd(&stats[0], 1);
-        atomicMax(&stats[1], L);
+        if (zeros) atomicAdd(&stats[0], zeros);
+        if (mx) atomicMax(&stats[1], mx);
     }
 }
 
@@ -461,7 +471,8 @@ chebdav_status build_graph(const int64_t *edges, int64_t E, int64_t n, int on_de
         cleanup();
         return fail(CHEBDAV_ENOMEM, "col allocation failed (%lld entries)", (long long)nnz);
     }
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)wave_blocks), dim3(256), 0, st, c_off, c_ucnt, c_buf,
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)std::min<int64_t>(wave_blocks, 2048)), dim3(256), 0, st, c_off,
+                       c_ucnt, c_buf,
                        g->row_ptr, g->col, g->deg, g->dinv, g->dinv32, n,
                        static_cast<int *>(stats.p));
     int hstats[2] = {0, 0};
