@@ -145,10 +145,21 @@ __global__ void __launch_bounds__(512) k_tridiag(const double *__restrict__ H, i
 
 // Sum over a group of P consecutive lanes (P = 16: DPP row rotations; P = 32:
 // plus one exchange between the two 16-lane rows), the same value in every lane.
+// The exchange is v_permlane16_swap on both halves of the double (a VALU op,
+// no LDS round trip): called with the same value twice it returns, in every
+// lane of a 32-lane half, the even row's sum as x and the odd row's as y, so
+// x + y is the group sum, added in the same order in every lane.
 template <int P>
 __device__ inline double group_sum(double v) {
     v = row16_sum(v);
-    if constexpr (P == 32) v += __shfl_xor(v, 16, kWave);
+    if constexpr (P == 32) {
+        const uint64_t u = (uint64_t)__double_as_longlong(v);
+        const auto lo = __builtin_amdgcn_permlane16_swap((uint32_t)u, (uint32_t)u, false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap((uint32_t)(u >> 32), (uint32_t)(u >> 32), false, false);
+        const double x = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+        const double y = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+        v = x + y;
+    }
     return v;
 }
 
