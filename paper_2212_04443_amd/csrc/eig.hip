@@ -271,7 +271,10 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
         if (pr == 0) kp[pc] = kpart;
         __syncthreads();
         // w = p - (t/2)(p^T v) v;  A <- A - v w^T - w v^T
-        // p^T v: the P row-group shares, summed across the P lanes of a group
+        // p^T v: the P row-group shares, summed across the P lanes of a group.
+        // Finished columns j <= k need no guard: there q_j = 0 and v_j = 0, so
+        // w_j = 0 and their entries (the stored reflectors) change by exactly 0;
+        // finished rows likewise have v_i = 0 and w_i = 0.
         const double ktot = group_sum<P>(kp[pr]);
         const double K = 0.5 * t * ktot;
 #pragma unroll
@@ -280,7 +283,7 @@ __global__ void __launch_bounds__(P * P) k_tridiag_reg(const double *__restrict_
             const double wr = ps[pr + P * a] - K * vr[a];
 #pragma unroll
             for (int b = 0; b < T; ++b)
-                if (P * (b + 1) - 1 > k && pc + P * b > k) A[a][b] -= vr[a] * (q[b] - K * vc[b]) + wr * vc[b];
+                if (P * (b + 1) - 1 > k) A[a][b] -= vr[a] * (q[b] - K * vc[b]) + wr * vc[b];
         }
     }
     __syncthreads();
