@@ -18,6 +18,11 @@
  *     graph build, orthonormalize, solve) synchronize that stream before they
  *     return; chebdav_spmm and chebdav_filter do not.
  *   - On error the contents of output buffers are unspecified; nothing leaks.
+ *   - Threads: a graph handle is read-only after chebdav_build_laplacian and may
+ *     be shared.  Calls from different host threads, each on its own stream with
+ *     its own workspace and outputs, may run concurrently: the library keeps no
+ *     mutable global state (its small pinned host scratch and the error text are
+ *     per thread).  Results do not depend on the interleaving.
  */
 #ifndef CHEBDAV_H
 #define CHEBDAV_H

@@ -218,3 +218,41 @@ def test_streaming_warm_start(cd, oracle_mod, dev):
     assert np.sqrt((R * R).sum(0)).max() <= 1e-8
     assert np.abs(ev - rnd.evals.cpu().numpy()).max() <= 1e-10
     assert warm.stats["iterations"] < rnd.stats["iterations"]
+
+
+def test_concurrent_solves_two_threads(cd, dev):
+    """Two host threads solve at the same time, each on its own stream with its
+    own workspace and the graph handle shared: the library keeps no mutable
+    global state (per-thread pinned scratch and error text), so each result
+    equals the sequential solve bit for bit."""
+    import threading
+    import torch
+    n = 20_000
+    e, _ = synth.sbm(n, 8, d_in=20, d_out=4, uneven=True, seed=11)
+    g = cd.build_laplacian(e, n)
+    params = [cd.make_params(k_want=8, kb=8, m=11, seed=s) for s in (1, 2)]
+    ref = []
+    for p in params:
+        r = cd.solve(g, p)
+        ref.append((r.evals.cpu().numpy(), r.evecs.cpu().numpy()))
+    out, errs = [None, None], []
+
+    def run(i):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                r = cd.solve(g, params[i], stream=s)
+                s.synchronize()
+                out[i] = (r.evals.cpu().numpy(), r.evecs.cpu().numpy())
+        except Exception as ex:  # reported below
+            errs.append(ex)
+
+    threads = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for i in range(2):
+        assert np.array_equal(out[i][0], ref[i][0])
+        assert np.array_equal(out[i][1], ref[i][1])
