@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     CHEBDAV_OK = 0,
     CHEBDAV_EINVAL = -1,       /* invalid argument (sizes, ids, interval, NaN input, ...) */
-    CHEBDAV_ENOMEM = -2,       /* device allocation failed or workspace too small */
+    CHEBDAV_ENOMEM = -2,       /* device allocation failed, workspace NULL or too small */
     CHEBDAV_EHIP = -3,         /* a HIP runtime call failed */
     CHEBDAV_ENOCONV = -4,      /* itmax reached: partial results are returned */
     CHEBDAV_EBREAKDOWN = -5,   /* no independent vector found after repeated replacement */

@@ -690,7 +690,7 @@ chebdav_status small_eig(const double *H, int64_t ldh, int n, double *evals, dou
     if (n < 1 || n > kMaxN) return fail(CHEBDAV_EUNSUPPORTED, "eigenproblem size %d outside [1, %d]", n, kMaxN);
     if (ldh < n || ldy < n) return fail(CHEBDAV_EINVAL, "leading dimension < n");
     const size_t need = eig_ws_bytes(n);
-    if (ws_bytes < need) return fail(CHEBDAV_ENOMEM, "eig workspace too small (%zu < %zu)", ws_bytes, need);
+    if (!ws || ws_bytes < need) return fail(CHEBDAV_ENOMEM, "eig workspace too small (%zu < %zu)", ws_bytes, need);
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;

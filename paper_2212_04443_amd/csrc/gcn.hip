@@ -341,7 +341,7 @@ chebdav_status gcn_forward(const Graph *g, const int dims[4], const float *X0, c
                            float *out, void *ws, size_t ws_bytes, hipStream_t st) {
     CD_TRY(check_dims(dims));
     const int64_t n = g->n;
-    if (ws_bytes < gcn_ws_bytes(n, dims)) return fail(CHEBDAV_ENOMEM, "GCN workspace too small");
+    if (!ws || ws_bytes < gcn_ws_bytes(n, dims)) return fail(CHEBDAV_ENOMEM, "GCN workspace too small");
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
@@ -367,7 +367,7 @@ chebdav_status gcn_backward(const Graph *g, const int dims[4], const float *X0, 
                             hipStream_t st) {
     CD_TRY(check_dims(dims));
     const int64_t n = g->n;
-    if (ws_bytes < gcn_ws_bytes(n, dims)) return fail(CHEBDAV_ENOMEM, "GCN workspace too small");
+    if (!ws || ws_bytes < gcn_ws_bytes(n, dims)) return fail(CHEBDAV_ENOMEM, "GCN workspace too small");
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
@@ -447,7 +447,7 @@ chebdav_status subspace_loss(const float *X, int64_t ldx, const double *U, int64
                              double *loss_host, float *dX, int64_t lddx, void *ws, size_t ws_bytes, hipStream_t st) {
     if (kx < 1 || kx > kMaxK || ku < 1 || ku > kMaxK) return fail(CHEBDAV_EUNSUPPORTED, "loss widths must be in [1, 64]");
     if (n < kx) return fail(CHEBDAV_EINVAL, "n < kx");
-    if (ws_bytes < loss_ws_bytes(n, kx, ku)) return fail(CHEBDAV_ENOMEM, "loss workspace too small");
+    if (!ws || ws_bytes < loss_ws_bytes(n, kx, ku)) return fail(CHEBDAV_ENOMEM, "loss workspace too small");
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;
@@ -529,7 +529,7 @@ chebdav_status rayleigh_ritz(const Graph *g, const float *X, int64_t ldx, int k,
                              int64_t ldv, double *ritz, void *ws, size_t ws_bytes, hipStream_t st) {
     const int64_t n = g->n;
     if (k < 1 || k > update_max_inplace_cols()) return fail(CHEBDAV_EUNSUPPORTED, "k must be in [1, 64]");
-    if (ws_bytes < rr_ws_bytes(n, k)) return fail(CHEBDAV_ENOMEM, "Rayleigh-Ritz workspace too small");
+    if (!ws || ws_bytes < rr_ws_bytes(n, k)) return fail(CHEBDAV_ENOMEM, "Rayleigh-Ritz workspace too small");
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;

@@ -127,7 +127,7 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
         CD_TRY(tsqr_ws_bytes(n, kb, &tb));
     }
     const size_t need = orth_ws_bytes(n, V.cols(), kb, method);
-    if (ws_bytes < need) return fail(CHEBDAV_ENOMEM, "orthonormalize workspace too small (%zu < %zu)", ws_bytes, need);
+    if (!ws || ws_bytes < need) return fail(CHEBDAV_ENOMEM, "orthonormalize workspace too small (%zu < %zu)", ws_bytes, need);
     Arena a;
     a.base = static_cast<char *>(ws);
     a.cap = ws_bytes;

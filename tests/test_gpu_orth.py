@@ -92,3 +92,38 @@ def test_strided_unaligned_views(cd, dev, n, ksub, kb, ldv, ldx, offv, offx):
     assert np.linalg.norm(V.T @ Q, 2) <= 10 * ksub * EPS
     Xp = X - V @ (V.T @ X)
     assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-12 * np.linalg.norm(Xp)
+
+
+def test_argument_errors_launch_nothing(cd, dev):
+    """Rejected calls return their status before any kernel runs: block wider
+    than 64 columns, no room for an orthonormal block, unknown method, NULL or
+    short workspace (orthonormalizer and small eigensolver)."""
+    import ctypes
+    import torch
+    L = cd._lib
+    n, ksub = 1000, 8
+    V = torch.zeros((n, ksub), dtype=torch.float64, device="cuda")
+    X = torch.zeros((n, 70), dtype=torch.float64, device="cuda")
+    rep = ctypes.c_int(-1)
+    null = ctypes.c_void_p(0)
+
+    def orth(kb, nn, method, ws, ws_bytes, ks=ksub):
+        return L.chebdav_orthonormalize(ctypes.c_void_p(V.data_ptr()), ksub, ks, ctypes.c_void_p(X.data_ptr()),
+                                        70, kb, nn, 0, 0, method, ctypes.byref(rep), ws, ws_bytes, null)
+
+    need = ctypes.c_size_t()
+    assert L.chebdav_orthonormalize_workspace_size(n, ksub, 16, cd.ORTH_CHOLQR, ctypes.byref(need)) == cd.OK
+    ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+    wsp = ctypes.c_void_p(ws.data_ptr())
+    assert orth(65, n, cd.ORTH_CHOLQR, wsp, need.value) == cd.EUNSUPPORTED
+    assert orth(16, 20, cd.ORTH_CHOLQR, wsp, need.value) == cd.EINVAL  # n < ksub + kb
+    assert orth(16, n, 7, wsp, need.value) == cd.EINVAL
+    assert orth(16, n, cd.ORTH_CHOLQR, null, need.value) == cd.ENOMEM
+    assert orth(16, n, cd.ORTH_CHOLQR, wsp, need.value - 1) == cd.ENOMEM
+    assert rep.value == -1  # untouched on error
+    H = torch.eye(40, dtype=torch.float64, device="cuda")
+    w = torch.empty(40, dtype=torch.float64, device="cuda")
+    Y = torch.empty((40, 40), dtype=torch.float64, device="cuda")
+    assert L.chebdav_small_eig(ctypes.c_void_p(H.data_ptr()), 40, 40, ctypes.c_void_p(w.data_ptr()),
+                               ctypes.c_void_p(Y.data_ptr()), 40, null, 1 << 30, null) == cd.ENOMEM
+    torch.cuda.synchronize()
