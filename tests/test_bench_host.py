@@ -1,0 +1,41 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic bytes of the sparse
+step, and the rule that the measured HBM traffic is reported only while the
+stored counter summary was taken on the current kernel source."""
+
+import hashlib
+import json
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_bytes_per_step_formula():
+    # sbm200k: CSR pattern 4 nnz + row_ptr 8 (n+1) + dinv 8 n + three n x kb FP64 blocks
+    n, nnz, kb = 200_000, 4_802_318, 32
+    assert bench.bytes_per_step(n, nnz, kb, 8) == 4 * nnz + 8 * (n + 1) + 8 * n + 3 * n * kb * 8 == 176_009_280
+    # FP32 blocks and dinv32
+    assert bench.bytes_per_step(n, nnz, kb, 4) == 4 * nnz + 8 * (n + 1) + 4 * n + 3 * n * kb * 4
+
+
+def test_committed_traffic_matches_kernel_source():
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_cheb_step_sbm200k_traffic.json")))
+    src = open(os.path.join(ROOT, "paper_2212_04443_amd", "csrc", "spmm.hip"), "rb").read()
+    assert rec["source_sha256"] == hashlib.sha256(src).hexdigest()
+    t = bench.measured_traffic("sbm200k", 32, 200_000)
+    assert t is not None and 1e8 < t < 1e9
+
+
+def test_traffic_dropped_when_source_differs(tmp_path, monkeypatch):
+    # a copy of the tree whose kernel source differs from the one the counters were taken on
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "paper_2212_04443_amd" / "csrc").mkdir(parents=True)
+    rec = json.load(open(os.path.join(ROOT, "profiles", "k_cheb_step_sbm200k_traffic.json")))
+    (tmp_path / "profiles" / "k_cheb_step_sbm200k_traffic.json").write_text(json.dumps(rec))
+    (tmp_path / "paper_2212_04443_amd" / "csrc" / "spmm.hip").write_text("// changed\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("sbm200k", 32, 200_000) is None
+    assert bench.measured_traffic("no_such_workload", 32, 200_000) is None
