@@ -128,17 +128,34 @@ def sbm(n: int, n_blocks: int, *, p_in=None, p_out=None, d_in=None, d_out=None,
 # ---------------------------------------------------------------------------
 def chung_lu_weights(n: int, gamma: float, mean_degree: float, cap: float) -> np.ndarray:
     """Expected-degree sequence w_i = c (i + 1)^(-1/(gamma-1)), capped at `cap`,
-    with c chosen (bisection) so that mean(w) = mean_degree.  Hubs first."""
+    with c chosen (bisection) so that mean(w) = mean_degree.  Hubs first.  The
+    bisection stops once an iteration leaves its bracket unchanged: every later
+    iteration would repeat it, so c is the bisection's limit."""
     x = np.arange(1, n + 1, dtype=np.float64) ** (-1.0 / (gamma - 1.0))
     lo, hi = 0.0, mean_degree * n
     for _ in range(200):
         c = 0.5 * (lo + hi)
         m = np.minimum(c * x, cap).mean()
-        if m < mean_degree:
-            lo = c
-        else:
-            hi = c
+        nlo, nhi = (c, hi) if m < mean_degree else (lo, c)
+        if nlo == lo and nhi == hi:
+            break
+        lo, hi = nlo, nhi
     return np.minimum(0.5 * (lo + hi) * x, cap)
+
+
+def _search_threads(cdf: np.ndarray, r: np.ndarray, threads: int = 16) -> np.ndarray:
+    """np.searchsorted(cdf, r, side="right") over chunks of r on a thread pool
+    (the search releases the interpreter lock); the result is the same array."""
+    from concurrent.futures import ThreadPoolExecutor
+    out = np.empty(r.shape, dtype=np.int64)
+    step = max(1, -(-len(r) // threads))
+
+    def one(a):
+        out[a:a + step] = np.searchsorted(cdf, r[a:a + step], side="right")
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(one, range(0, len(r), step)))
+    return out
 
 
 def chung_lu(n: int, *, gamma: float = 2.1, mean_degree: float = 16.0, cap=None,
@@ -152,7 +169,7 @@ def chung_lu(n: int, *, gamma: float = 2.1, mean_degree: float = 16.0, cap=None,
     largest connected component, relabelled order-preserving (hubs first).
 
     Returns (edges, n_nodes)."""
-    from scipy.sparse import coo_matrix
+    from scipy.sparse import csr_matrix
     from scipy.sparse.csgraph import connected_components
 
     if cap is None:
@@ -163,8 +180,8 @@ def chung_lu(n: int, *, gamma: float = 2.1, mean_degree: float = 16.0, cap=None,
     n_pairs = int(rng.poisson(s / 2.0))
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
-    u = np.searchsorted(cdf, rng.random(n_pairs), side="right").astype(np.int64)
-    v = np.searchsorted(cdf, rng.random(n_pairs), side="right").astype(np.int64)
+    u = _search_threads(cdf, rng.random(n_pairs))
+    v = _search_threads(cdf, rng.random(n_pairs))
     np.minimum(u, n - 1, out=u)
     np.minimum(v, n - 1, out=v)
     keep = u != v
@@ -175,7 +192,10 @@ def chung_lu(n: int, *, gamma: float = 2.1, mean_degree: float = 16.0, cap=None,
     edges = np.stack([key // n, key % n], axis=1).astype(np.int64)
     if not lcc:
         return np.ascontiguousarray(edges), n
-    a = coo_matrix((np.ones(len(edges), dtype=np.int8), (edges[:, 0], edges[:, 1])), shape=(n, n))
+    # the keys are sorted, so the upper-triangle pattern is already in row order
+    indptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(edges[:, 0], minlength=n), out=indptr[1:])
+    a = csr_matrix((np.ones(len(edges), dtype=np.int8), edges[:, 1].astype(np.int32), indptr), shape=(n, n))
     _, comp = connected_components(a, directed=False)
     big = np.argmax(np.bincount(comp))
     in_lcc = comp == big
