@@ -3,8 +3,8 @@
 to judge a partition against the planted blocks.
 
 Readings (the paper names K-means and row normalization only):
-  * a row's norm sums the squares in ascending coordinate order; a zero row of
-    the eigenvector block stays zero after normalization;
+  * a row is divided by its 2-norm (the plain definition; no summation order
+    is implied); a zero row of the eigenvector block stays zero;
   * K-means is Lloyd's iteration (assign every row to its nearest centre by
     squared Euclidean distance, ties to the lower centre index; move every
     centre to the mean of its rows; a centre with no rows stays where it is),
@@ -29,14 +29,9 @@ from .philox import philox4x32_10
 
 
 def row_normalize(U: np.ndarray) -> np.ndarray:
-    """Each row divided by its 2-norm (squares summed in ascending coordinate
-    order, one rounded product and sum each; then one rounded square root and
-    division per entry); zero rows stay zero."""
+    """Each row divided by its 2-norm; zero rows stay zero."""
     U = np.asarray(U, dtype=np.float64)
-    s = np.zeros(U.shape[0])
-    for j in range(U.shape[1]):
-        s = s + U[:, j] * U[:, j]
-    nr = np.sqrt(s)
+    nr = np.sqrt((U * U).sum(axis=1))
     out = np.zeros_like(U)
     nz = nr > 0.0
     out[nz] = U[nz] / nr[nz, None]

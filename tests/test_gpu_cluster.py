@@ -2,12 +2,15 @@
 against the oracle's FP64 restatement on the same inputs, its edge cases, and
 the whole spectral-clustering pipeline on planted SBM graphs.
 
-Bar: labels identical to the oracle's (both sides take every nearest-centre
-decision in FP64 with the same coordinate order; the row sums behind the
-centres differ only in their summation order, so a label could differ only for
-a row equidistant from two centres to rounding, which these inputs do not
-have), centres within 1e-12 absolute, equal round counts, inertia within
-1e-10 relative."""
+Bar: labels identical to the oracle's, except at a row that is equidistant from
+the two centres concerned to rounding (relative gap of the squared distances
+<= 1e-12): the row norms and centre sums are rounded differently on the two
+sides, so such a tie may be broken either way, and the K-means rounds after it
+then legitimately follow another path.  With identical labels: centres within
+1e-12 absolute, equal round counts, inertia within 1e-10 relative.  After a
+tie: the GPU's own result must be consistent (each centre the mean of its rows
+within 1e-12, every row at a nearest centre up to a tie, inertia the sum of its
+squared distances within 1e-10)."""
 
 import numpy as np
 import pytest
@@ -16,11 +19,25 @@ import synth
 
 pytestmark = pytest.mark.gpu
 
+TIE_GAP = 1e-12
+
 
 @pytest.fixture(scope="module")
 def ocl(oracle_mod):
     from oracle import cluster
     return cluster
+
+
+def _dist_table(ocl, F, C):
+    return np.stack([ocl.sq_dist(F, C[c]) for c in range(C.shape[0])], axis=1)
+
+
+def _ties_only(D, a, b):
+    """Rows where labels a and b differ are ties under the distance table D."""
+    rows = np.nonzero(a != b)[0]
+    da, db = D[rows, a[rows]], D[rows, b[rows]]
+    gap = np.abs(da - db) / np.maximum(np.maximum(da, db), 1e-300)
+    return bool((gap <= TIE_GAP).all()), rows
 
 
 def _compare(cd, ocl, U, K, seed, max_iter=100):
@@ -30,10 +47,27 @@ def _compare(cd, ocl, U, K, seed, max_iter=100):
     labels, C = labels.cpu().numpy(), C.cpu().numpy()
     F = ocl.row_normalize(U)
     wl, wC, wr, wi = ocl.kmeans(F, K, seed=seed, max_iter=max_iter)
-    assert np.array_equal(labels, wl)
-    assert np.abs(C - wC).max() <= 1e-12
-    assert rounds == wr
-    assert abs(inertia - wi) <= 1e-10 * max(wi, 1e-300)
+    if np.array_equal(labels, wl):
+        assert np.abs(C - wC).max() <= 1e-12
+        assert rounds == wr
+        assert abs(inertia - wi) <= 1e-10 * max(wi, 1e-300)
+        return labels, C, rounds, inertia
+    # a tie was broken the other way: the final labels may differ only at ties,
+    # and the GPU's result must be a consistent K-means state of its own
+    ok, rows = _ties_only(_dist_table(ocl, F, wC), labels, wl)
+    print("labels differ from the oracle's at %d rows (ties: %s)" % (len(rows), ok))
+    assert ok
+    D = _dist_table(ocl, F, C)
+    for c in range(K):
+        mem = labels == c
+        if mem.any():
+            assert np.abs(C[c] - F[mem].sum(axis=0) / mem.sum()).max() <= 1e-12
+    if rounds < max_iter:
+        best = D.min(axis=1)
+        mine = D[np.arange(len(labels)), labels]
+        assert ((mine - best) <= TIE_GAP * np.maximum(mine, 1e-300)).all()
+    want = float(D[np.arange(len(labels)), labels].sum())
+    assert abs(inertia - want) <= 1e-10 * max(want, 1e-300)
     return labels, C, rounds, inertia
 
 
@@ -89,16 +123,16 @@ def test_cluster_deterministic(cd, dev):
 def test_spectral_pipeline(cd, ocl, dev, workload):
     """Graph -> eigenvectors (GPU solver) -> clustering tail: the tail agrees with
     the oracle's on the GPU eigenvectors, and the partition recovers the planted
-    blocks (ARI and NMI reported; the bar is the oracle's own score on the same
-    vectors, which the identical labels imply)."""
+    blocks (ARI and NMI reported, and recomputed by the oracle's own scores)."""
     from paper_2212_04443_amd import spectral
     e, n, cfg = synth.make_config_graph(workload)
     g = cd.build_laplacian(e, n)
     out = spectral.spectral_clustering(g, cfg["k"], kb=cfg["kb"], m=cfg["m"], seed=1)
     U = out["evecs"].cpu().numpy()
     labels = out["labels"].cpu().numpy()
-    wl, *_ = ocl.kmeans(ocl.row_normalize(U), cfg["k"], seed=1)
-    assert np.array_equal(labels, wl)
+    F = ocl.row_normalize(U)
+    wl, wC, *_ = ocl.kmeans(F, cfg["k"], seed=1)
+    assert _ties_only(_dist_table(ocl, F, wC), labels, wl)[0]
     truth = cfg["labels"]
     a, m = spectral.adjusted_rand_index(labels, truth), spectral.normalized_mutual_info(labels, truth)
     print("%s: ARI %.4f NMI %.4f, %d K-means rounds, solve %.1f ms, cluster %.1f ms"
