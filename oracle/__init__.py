@@ -13,7 +13,7 @@ against exact rational arithmetic; the filter against the closed form
 Q p_m(Lambda) Q^T X and cycle-graph Fourier modes; orthonormalization against
 its invariants; the solver against dense eigendecomposition and closed-form
 spectra (cycle, path, complete, complete bipartite, hypercube); Philox against
-its published known-answer vectors; the tall-skinny QR (tsqr.py, Sec. 5) against
+its published known-answer vectors; the tall-skinny QR (tsqr.py, Sec. 3.3) against
 a hand-worked factorization, LAPACK's QR and the Cholesky factor of X^T X.  Parity unpinned: the dependence threshold
 1e-10 of the orthonormalizer (the paper gives none), and iteration counts
 (the paper prints none).

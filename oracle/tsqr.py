@@ -1,6 +1,6 @@
 """Oracle (test infrastructure): tall-skinny QR.
 
-Sec. 5 orthonormalizes distributed blocks with the parallel TSQR of Demmel et
+Sec. 3.3 orthonormalizes distributed blocks with the parallel TSQR of Demmel et
 al.: every row block is factored on its own, the R factors of q neighbouring
 blocks are stacked in block order and factored again, up a tree, until one R
 is left; Q is the product of the block-diagonal intermediate Q factors.  Only

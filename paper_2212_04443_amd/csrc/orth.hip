@@ -14,11 +14,13 @@
 //             columns before it).  Dependent columns are replaced by Philox
 //             columns and everything is redone.
 //   BCGS      one more pass against V when the smallest scaled pivot is below
-//             0.01 (R^{-1} may then amplify the remaining non-orthogonality to
-//             V above rounding level), then a second, plain CholQR; otherwise
-//             one Newton-Schulz step X <- X (3 I - X^T X) / 2 in its place.
+//             0.01 or the bound sqrt(kb) ||R^{-1}||_F on the condition number
+//             of the scaled factor exceeds 100 (R^{-1} may then amplify the
+//             remaining non-orthogonality to V above rounding level), then a
+//             second, plain CholQR; otherwise one Newton-Schulz step
+//             X <- X (3 I - X^T X) / 2 in its place.
 // With CHEBDAV_ORTH_TSQR the two Cholesky QRs are replaced by Householder TSQR
-// (Sec. 5): R of the projected block decides dependence with the same
+// (Sec. 3.3): R of the projected block decides dependence with the same
 // thresholds (column norms from R's columns, scaled pivots R_jj / ||R(:, j)||),
 // then X <- Q; the third projection is followed by a second TSQR.  TSQR needs
 // no condition-number bound, at about ten times the cost of Cholesky QR.
@@ -154,10 +156,11 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
     }
     CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
     // a third projection only when R^{-1} can have amplified the remaining
-    // components along V above rounding level (smallest scaled pivot < 0.01);
-    // then a second Cholesky QR.  Otherwise the first Cholesky QR left X^T X
-    // within O(kappa^2 eps) of I with kappa below about 100, and one
-    // Newton-Schulz step X (3 I - X^T X) / 2 squares that deviation.
+    // components along V above rounding level (smallest scaled pivot < 0.01, or
+    // the condition bound sqrt(kb) ||R^{-1}||_F of the scaled factor above
+    // 100); then a second Cholesky QR.  Otherwise the first Cholesky QR left
+    // X^T X within O(kappa^2 eps) of I with kappa <= 100, and one Newton-Schulz
+    // step X (3 I - X^T X) / 2 squares that deviation.
     if (hdep[kb + 1]) {
         CD_TRY(project_out(V, X, ldx, kb, n, s, st));
         CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));

@@ -115,6 +115,29 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
             const int i = ti + P * a, j = tj + P * b;
             if (i < kb && j < kb) Rinv[i * kb + j] = s[i] * (i < j ? A[j][i] : i == j ? bd[i] : 0.0);
         }
+    // ||R^{-1}||_F^2 of the column-scaled factor (its columns have unit norm,
+    // so kappa(R) <= sqrt(kb) ||R^{-1}||_F): per-thread sums over a fixed set of
+    // entries, then a fixed-order tree (deterministic)
+    __shared__ double fro[256];
+    {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < TT; ++a)
+#pragma unroll
+            for (int b = 0; b < TT; ++b) {
+                const int i = ti + P * a, j = tj + P * b;
+                if (i < kb && j < kb && i <= j) {
+                    const double v = i < j ? A[j][i] : bd[i];
+                    acc += v * v;
+                }
+            }
+        fro[tid] = acc;
+    }
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) fro[tid] += fro[tid + h];
+        __syncthreads();
+    }
     if (tid == 0) {
         int any = 0;
         double rmin = 1.0;
@@ -123,7 +146,11 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
             if (!d[j]) rmin = fmin(rmin, dR[j]);
         }
         dep[kb] = any;
-        dep[kb + 1] = rmin < 0.01;
+        // a second full pass unless kappa(R) <= 100 is certain: then the first
+        // pass left X^T X within about kappa^2 eps of I and V^T X within about
+        // kappa eps, and one Newton-Schulz step suffices
+        const double kappa2 = (double)kb * fro[0];
+        dep[kb + 1] = rmin < 0.01 || !(kappa2 <= 1e4);
     }
     if (tid < kb) dep[tid] = d[tid];
 }

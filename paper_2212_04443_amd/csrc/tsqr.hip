@@ -1,4 +1,4 @@
-// Tall-skinny QR by a tree of Householder factorizations (Sec. 5, distributed
+// Tall-skinny QR by a tree of Householder factorizations (Sec. 3.3, distributed
 // orthonormalization: the TSQR of Demmel et al. as its parallel-TSQR algorithm
 // states it, with the row blocks of one GPU in place of processes).
 //
@@ -213,7 +213,8 @@ __global__ void k_tsqr_rsign(const double *__restrict__ Rtop, int kb, double *__
 // r_j^2 <= 1e-13.  dep[kb] = any, dep[kb + 1] = smallest r_j of the others < 0.01.
 __global__ void k_tsqr_dep(const double *__restrict__ R, int64_t ldr, int kb, const double *__restrict__ norm0,
                            int *__restrict__ dep) {
-    __shared__ double piv[kTsqrMaxKb];
+    __shared__ double piv[kTsqrMaxKb], cn[kTsqrMaxKb], fro[kTsqrMaxKb];
+    __shared__ double xs[kTsqrMaxKb][kTsqrMaxKb + 1];  // column j of the inverse of R S^{-1} in xs[.][j]
     __shared__ int d[kTsqrMaxKb];
     const int j = threadIdx.x;
     if (j < kb) {
@@ -224,19 +225,40 @@ __global__ void k_tsqr_dep(const double *__restrict__ R, int64_t ldr, int kb, co
         const double r = bad ? 0.0 : R[j * ldr + j] / x;
         if (!bad && !(r * r > 1e-13)) bad = true;
         piv[j] = r;
+        cn[j] = bad ? 1.0 : x;
         d[j] = bad;
         dep[j] = bad;
     }
     __syncthreads();
+    // ||(R S^{-1})^{-1}||_F^2 with S = diag of R's column norms (the scaled factor
+    // has unit-norm columns, so its condition number is at most sqrt(kb) times
+    // that norm): thread j solves for column j by back-substitution
+    if (j < kb) {
+        double f = 0.0;
+        const double rjj = piv[j];
+        xs[j][j] = rjj != 0.0 ? 1.0 / rjj : 0.0;
+        f = xs[j][j] * xs[j][j];
+        for (int i = j - 1; i >= 0; --i) {
+            double acc = 0.0;
+            for (int l = i + 1; l <= j; ++l) acc += (R[i * ldr + l] / cn[l]) * xs[l][j];
+            const double rii = piv[i];
+            xs[i][j] = rii != 0.0 ? -acc / rii : 0.0;
+            f += xs[i][j] * xs[i][j];
+        }
+        fro[j] = f;
+    }
+    __syncthreads();
     if (j == 0) {
         int any = 0;
-        double rmin = 1.0;
+        double rmin = 1.0, f = 0.0;
         for (int i = 0; i < kb; ++i) {
             any |= d[i];
             if (!d[i]) rmin = fmin(rmin, piv[i]);
+            f += fro[i];
         }
         dep[kb] = any;
-        dep[kb + 1] = rmin < 0.01;
+        // a second pass (projection, then TSQR again) unless kappa <= 100 is certain
+        dep[kb + 1] = rmin < 0.01 || !((double)kb * f <= 1e4);
     }
 }
 

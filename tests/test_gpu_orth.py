@@ -49,6 +49,45 @@ def test_ill_conditioned_mostly_in_span(cd, dev):
     assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-9 * np.linalg.norm(Xp)
 
 
+def _kahan(kb, s):
+    """Kahan's upper-triangular matrix diag(1, s, .., s^(kb-1)) (I - c U), c^2 + s^2 = 1,
+    U the strictly upper ones: unit-norm columns, scaled pivots s^j, and a
+    condition number growing like ((1 + c)/s)^kb."""
+    c = np.sqrt(1.0 - s * s)
+    return np.diag(s ** np.arange(kb)) @ (np.eye(kb) - c * np.triu(np.ones((kb, kb)), 1))
+
+
+@pytest.mark.parametrize("method", ["cholqr", "tsqr"])
+def test_graded_block_pivots_above_threshold(cd, dev, method):
+    """A graded block whose scaled Cholesky pivots all stay >= 0.01 but whose
+    condition number is 1.2e5 (Kahan's matrix, kb = 16): the first Cholesky QR
+    alone would leave X^T X about kappa^2 eps away from I and V^T X about kappa
+    eps, so the orthonormalizer must take its full second pass."""
+    n, ksub, kb = 20_000, 48, 16
+    V = _basis(n, ksub, 21)
+    K = _kahan(kb, 0.78)
+    assert (0.78 ** np.arange(kb)).min() >= 0.01 and np.linalg.cond(K) >= 1e5
+    Q0 = _basis(n, ksub + kb, 22)[:, ksub:]
+    Q0 = Q0 - V @ (V.T @ Q0)
+    Q0, _ = np.linalg.qr(Q0)
+    X = Q0 @ K + V @ np.random.default_rng(23).standard_normal((ksub, kb))
+    print("case graded block %s" % method, flush=True)
+    Q, rep = _run_m(cd, V, X, method)
+    assert rep == 0
+    assert np.linalg.norm(Q.T @ Q - np.eye(kb), 2) <= 10 * kb * EPS
+    assert np.linalg.norm(V.T @ Q, 2) <= 10 * ksub * EPS
+    Xp = X - V @ (V.T @ X)
+    assert np.linalg.norm(Xp - Q @ (Q.T @ Xp)) <= 1e-10 * np.linalg.norm(Xp)
+
+
+def _run_m(cd, V, X, method):
+    import torch
+    Vt = torch.from_numpy(V).cuda()
+    Xt = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    rep = cd.orthonormalize(Vt, Xt, method=method)
+    return Xt.cpu().numpy(), rep
+
+
 def test_exactly_dependent_columns(cd, oracle_mod, dev):
     n, kb = 1500, 6
     V = _basis(n, 10, 8)

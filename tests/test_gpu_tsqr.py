@@ -1,4 +1,4 @@
-"""GPU parity for the Householder TSQR (Sec. 5) against the oracle's flat
+"""GPU parity for the Householder TSQR (Sec. 3.3) against the oracle's flat
 Householder QR, element by element (both with a non-negative diagonal of R,
 which makes the thin QR unique): shapes that span one chunk, several chunks
 with a ragged tail, several tree levels, in place; rank-deficient blocks by

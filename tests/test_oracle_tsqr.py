@@ -1,4 +1,4 @@
-"""Pins for the oracle's tall-skinny QR (Sec. 5, distributed orthonormalization
+"""Pins for the oracle's tall-skinny QR (Sec. 3.3, distributed orthonormalization
 by TSQR): a hand-computed exact factorization, LAPACK's Householder QR with the
 same sign convention, the Cholesky factor of X^T X, orthogonal-column and
 rank-deficient closed forms, and the paper's tree (any leaf count and fan-in)
@@ -88,7 +88,7 @@ def test_tree_equals_flat(tq, n, k, p, q):
 
 
 def test_tree_on_paper_example(tq):
-    # the four-process, fan-in-two example of Sec. 5: R_0123 is the R of V
+    # the four-process, fan-in-two example of Sec. 3.3: R_0123 is the R of V
     X = np.random.default_rng(11).standard_normal((400, 6))
     _, Rf = tq.householder_qr(X)
     Q0123, R0123 = tq.tsqr_tree(X, 4, 2)
