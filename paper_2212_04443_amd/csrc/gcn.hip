@@ -168,13 +168,6 @@ __global__ void k_features(const int32_t *__restrict__ deg, double inv_mean_deg,
     }
 }
 
-__global__ void k_sum_deg(const int32_t *__restrict__ deg, int64_t n, unsigned long long *__restrict__ out) {
-    unsigned long long s = 0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) s += (unsigned long long)deg[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) atomicAdd(out, s);
-}
 
 // Loss and gradient coefficients from G = X^T X (kx x kx) and M = X^T U (kx x ku),
 // one workgroup: Cholesky of G, Ginv, L = 1 - tr(M^T Ginv M)/ku,
@@ -393,20 +386,9 @@ chebdav_status gcn_backward(const Graph *g, const int dims[4], const float *X0, 
 
 chebdav_status gcn_features(const Graph *g, uint64_t seed, int n_gauss, float *X, int64_t ldx, hipStream_t st) {
     if (n_gauss < 0 || ldx < n_gauss + 1) return fail(CHEBDAV_EINVAL, "bad feature width");
-    unsigned long long *d_sum = nullptr, h_sum = 0;
-    CD_HIP(hipMalloc(&d_sum, sizeof(*d_sum)));
-    chebdav_status rs = CHEBDAV_OK;
-    if (hipMemsetAsync(d_sum, 0, sizeof(*d_sum), st) != hipSuccess) rs = fail(CHEBDAV_EHIP, "memset failed");
-    if (rs == CHEBDAV_OK) {
-        hipLaunchKernelGGL(k_sum_deg, dim3(grid1(g->n)), dim3(256), 0, st, g->deg, g->n, d_sum);
-        if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(&h_sum, d_sum, sizeof(h_sum), hipMemcpyDeviceToHost, st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            rs = fail(CHEBDAV_EHIP, "degree sum failed");
-    }
-    (void)hipFree(d_sum);
-    if (rs != CHEBDAV_OK) return rs;
-    const double mean = h_sum > 0 ? (double)h_sum / (double)g->n : 1.0;
+    if (!X) return fail(CHEBDAV_EINVAL, "X is NULL");
+    // the degrees sum to the stored nonzeros, which the graph keeps on the host
+    const double mean = g->nnz > 0 ? (double)g->nnz / (double)g->n : 1.0;
     const int pairs = (n_gauss + 1) / 2;
     hipLaunchKernelGGL(k_features, dim3(grid1(g->n * (pairs + 1))), dim3(256), 0, st, g->deg, 1.0 / mean, g->n,
                        n_gauss, seed, X, ldx);
