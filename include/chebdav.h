@@ -48,7 +48,7 @@ typedef enum { CHEBDAV_F64 = 0, CHEBDAV_F32 = 1 } chebdav_dtype;
 
 /* Orthonormalization of a new block after its projections (Alg. 2 step 6):
  * Cholesky QR with a second pass (Cholesky QR or a Newton-Schulz step), or
- * Householder TSQR (Sec. 5). */
+ * Householder TSQR (Sec. 3.3). */
 typedef enum { CHEBDAV_ORTH_CHOLQR = 0, CHEBDAV_ORTH_TSQR = 1 } chebdav_orth;
 
 /* Opaque handle owning the device CSR pattern of S and its degree scaling. */
@@ -132,7 +132,8 @@ chebdav_status chebdav_filter(const chebdav_graph *g, const double *X, int64_t l
  * ksub == 0), and spans the same space as (I - V V^T) X_in when that has full
  * numerical rank.  Method: two block classical Gram-Schmidt passes against V,
  * then (method CHOLQR) Cholesky QR with a dependence test; when the smallest
- * diagonal entry of the scaled Cholesky factor is below 0.01, a third pass
+ * diagonal entry of the scaled Cholesky factor R is below 0.01, or the bound
+ * sqrt(kb) ||R^{-1}||_F on its condition number exceeds 100, a third pass
  * against V and a second Cholesky QR, otherwise one Newton-Schulz step
  * X <- X (3 I - X^T X) / 2 (X^T X is then within O(1e4 eps) of I, and the step
  * squares that deviation); or (method TSQR) the same with Householder TSQR
@@ -153,7 +154,7 @@ chebdav_status chebdav_orthonormalize(const double *V, int64_t ldv, int ksub, do
                                       void *workspace, size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
- * Tall-skinny QR (Sec. 5, distributed orthonormalization: TSQR over a tree of
+ * Tall-skinny QR (Sec. 3.3, distributed orthonormalization: TSQR over a tree of
  * row blocks, here the row chunks of one GPU).  X = Q R for X (n x kb, device
  * double, row-major, ldx >= kb; only read): Q (n x kb, device double,
  * row-major, ldq >= kb) with orthonormal columns, R (kb x kb, device double,
@@ -175,6 +176,19 @@ chebdav_status chebdav_tsqr(const double *X, int64_t ldx, int64_t n, int kb, dou
  * Solver (Alg. 2: block Chebyshev-Davidson with inner-outer restart and
  * progressive filtering of initial vectors).
  * ------------------------------------------------------------------------ */
+/* One Davidson iteration as seen after its restart decisions (Alg. 2 steps
+ * 10-16), passed to chebdav_params.log_cb: kc = pairs locked before this
+ * iteration's locking; kact = active columns after the inner restart (step 10);
+ * ksub = kc + kact; n_locked = pairs locked by this iteration (step 12);
+ * n_unlocked = pairs the exit certificate handed back for refinement; the
+ * restart flags; low_nwb = the filter cut this iteration used (step 5);
+ * min/max_residual over the residual norms of step 12. */
+typedef struct {
+    int iteration, kc, kact, ksub, n_locked, n_unlocked, inner_restart, outer_restart, filter_f32;
+    double low_nwb, min_residual, max_residual;
+} chebdav_iter_record;
+typedef void (*chebdav_log_fn)(const chebdav_iter_record *rec, void *user);
+
 typedef struct {
     int k_want;             /* number of smallest eigenpairs wanted (>= 1)                */
     int kb;                 /* block size: vectors filtered and added per iteration       */
@@ -194,6 +208,14 @@ typedef struct {
     uint64_t seed;          /* Philox key for all random vectors                           */
     int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
     chebdav_orth orth;      /* orthonormalization of new blocks (default CHOLQR)           */
+    int k_ro;               /* outer-restart size cap; 0 -> dim_max - 2 kb - kc (Sec. 2);
+                               > 0 -> min(k_ro, dim_max - 2 kb - kc)                       */
+    int refine_sweeps;      /* exit certificate: rounds of un-lock and refinement allowed
+                               before ENOCONV; 0 -> 3, < 0 -> none                          */
+    double certify_tol;     /* exit certificate: a returned pair needs a fresh
+                               ||A v - lambda v||_2 <= certify_tol; 0 -> tol               */
+    chebdav_log_fn log_cb;  /* nullable: called on the host once per iteration           */
+    void *log_user;         /* passed to log_cb unchanged                                  */
 } chebdav_params;
 
 typedef struct {
@@ -209,6 +231,10 @@ typedef struct {
     double t_total_ms;      /* wall time of the call                                       */
     double t_filter_ms;     /* with timing != 0: event-timed filter time (else 0)          */
     int n_filter_launches;  /* with timing != 0: filter step launches timed                */
+    int used_fallback;      /* 1 if the exit certificate un-locked a pair (refinement ran) */
+    int n_unlocked;         /* pairs un-locked by the exit certificate                     */
+    int n_inner_restarts;   /* Alg. 2 step 10 restarts                                     */
+    int n_outer_restarts;   /* Alg. 2 step 16 restarts                                     */
 } chebdav_stats;
 
 /* Device bytes needed by chebdav_solve for this graph and these parameters. */
@@ -222,9 +248,18 @@ chebdav_status chebdav_solve_workspace_size(const chebdav_graph *g, const chebda
  * evals: device double[k_want], ascending.
  * evecs: device double, n x k_want row-major (ld = k_want), orthonormal columns.
  * stats: host, may be NULL.
+ * Convergence (Alg. 2 step 12) is tested on the residuals the iteration keeps
+ * (W - V theta, W = A V maintained through the rotations).  Once k_want pairs
+ * are locked, an exit certificate recomputes ||A v - lambda v||_2 for the
+ * k_want smallest with a fresh sparse product; a pair above certify_tol is
+ * un-locked (at most kb per round, smallest eigenvalues first) and put at the
+ * front of the next block to filter, and the iteration continues in FP64 (at
+ * most refine_sweeps such rounds; stats->used_fallback, stats->n_unlocked).
  * Errors: EINVAL for invalid parameters (including dim_max < k_want + 2 kb + 1,
- * k_ri > act_max - kb, dim_max > n); ENOCONV when itmax is reached (the
- * converged pairs are still written; stats->converged tells how many). */
+ * k_ri > act_max - kb, dim_max > n); ENOCONV when itmax is reached or the
+ * certificate still fails after refine_sweeps rounds: the pairs found are still
+ * written (the smallest locked ones, ascending) and stats->converged counts
+ * those whose certificate passed. */
 chebdav_status chebdav_solve(const chebdav_graph *g, const chebdav_params *p,
                              const double *V_init, int k_init, double *evals, double *evecs,
                              chebdav_stats *stats, void *workspace, size_t ws_bytes,
@@ -256,7 +291,10 @@ chebdav_status chebdav_gcn_backward(const chebdav_graph *g, const int dims[4], c
 
 /* Input features X (device float, n x (n_gauss + 1), leading dimension ldx):
  * n_gauss standard normal channels (Box-Muller on Philox4x32-10, key = seed,
- * counter (row, row >> 32, channel pair, 1)) and sqrt(deg_i / mean degree). */
+ * counter (row, row >> 32, channel pair, 1)) and sqrt(deg_i / mean degree),
+ * mean degree = nnz / n.  One kernel, stream-ordered: no workspace, no
+ * allocation, no synchronization.  Errors: EINVAL (n_gauss < 0,
+ * ldx < n_gauss + 1, X NULL). */
 chebdav_status chebdav_gcn_features(const chebdav_graph *g, uint64_t seed, int n_gauss, float *X,
                                     int64_t ldx, void *hip_stream);
 

@@ -24,7 +24,16 @@ Readings of what the paper leaves open or prints inconsistently:
   * missing vectors (no or too few start vectors, V_init exhausted, fewer than
     kb - e_c active Ritz vectors) are filled with Philox columns numbered in the
     order they are drawn;
-  * itmax defaults to 1000; the k_want smallest locked pairs are returned.
+  * itmax defaults to 1000; the k_want smallest locked pairs are returned;
+  * exit certificate (Table 1 counts an extra SpMM for the residuals): once
+    k_want pairs are locked, ||A v - lambda v||_2 of the k_want smallest is
+    recomputed from a fresh product with A.  Pairs above certify_tol (default
+    tol) are un-locked, the smallest kb first, together with the locked pairs
+    above rank k_want - 1 (so that the loop goes on); they lead the next block
+    to filter, ahead of V_init columns and Ritz vectors.  After refine_sweeps
+    such rounds (default 3) a failing certificate ends the run unconverged;
+  * an outer restart keeps dim_max - 2 kb - kc columns, or k_ro if that is
+    smaller and positive.
 """
 
 from __future__ import annotations
@@ -53,6 +62,9 @@ class Params:
     lowb: float = 0.0
     low_nwb0: float | None = None
     seed: int = 0
+    k_ro: int = 0
+    refine_sweeps: int = 0
+    certify_tol: float = 0.0
 
 
 @dataclass
@@ -66,6 +78,9 @@ class Result:
     n_random: int
     max_residual: float
     history: list = field(default_factory=list)
+    certified: int = 0
+    n_unlocked: int = 0
+    status: str = "ok"
 
 
 def resolve_params(p: Params, n: int) -> Params:
@@ -78,6 +93,11 @@ def resolve_params(p: Params, n: int) -> Params:
         q.k_ri = max(q.act_max // 2, q.act_max - 3 * q.kb)
     if q.low_nwb0 is None:
         q.low_nwb0 = q.lowb + (q.upperb - q.lowb) * q.k_want / n
+    if q.refine_sweeps == 0:
+        q.refine_sweeps = 3
+    q.refine_sweeps = max(0, q.refine_sweeps)
+    if q.certify_tol <= 0:
+        q.certify_tol = q.tol
     if not (1 <= q.kb and 1 <= q.k_want <= n and q.m >= 1):
         raise ValueError("need kb >= 1, 1 <= k_want <= n, m >= 1")
     if not (1 <= q.k_ri <= q.act_max - q.kb):
@@ -128,6 +148,10 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
     it = 0
     n_filter = n_other = 0
     history = []
+    cert_rounds = 0
+    n_unlocked = 0
+    status = "noconv"
+    cert = None  # fresh residuals of the last certificate
     while it < p.itmax:
         it += 1
         # step 5: filter
@@ -154,7 +178,8 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
         D, Y = D[order], Y[:, order]
         kold = kact
         # step 10: inner restart
-        if kact + kb > p.act_max:
+        inner = kact + kb > p.act_max
+        if inner:
             kact = p.k_ri
             ksub = kc + kact
         # step 11: subspace rotation
@@ -168,7 +193,8 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
         conv = res <= p.tol
         ec = int(conv.sum())
         history.append(dict(iteration=it, kc=kc, kact=kact, ksub=ksub, low_nwb=low_nwb,
-                            res=res.copy(), ritz=D.copy(), ec=ec))
+                            res=res.copy(), ritz=D.copy(), ec=ec, inner_restart=inner,
+                            outer_restart=False, n_unlocked=0))
         if ec:
             conv_idx = np.nonzero(conv)[0]
             rest = np.array([i for i in range(kact) if not (i < nres and conv[i])], dtype=np.int64)
@@ -181,9 +207,37 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
             evals = evals[srt]
             V[:, :kc + ec] = V[:, srt]
             kc += ec
-        # step 13
+        # step 13, with the exit certificate
+        unlocked = np.zeros((n, 0))
         if kc >= p.k_want:
-            break
+            Vk = np.asfortranarray(V[:, :p.k_want])
+            Rk = apply_laplacian(csr, Vk) - Vk * evals[:p.k_want]
+            cert = np.sqrt(np.sum(Rk * Rk, axis=0))
+            n_other += 1
+            bad = [t for t in range(p.k_want) if not cert[t] <= p.certify_tol][:kb]
+            if not bad:
+                status = "ok"
+                break
+            if cert_rounds >= p.refine_sweeps:
+                status = "certificate"
+                break
+            cert_rounds += 1
+            out = set(bad)
+            for t in range(kc - 1, -1, -1):  # the largest locked pairs, until kc < k_want
+                if kc - len(out) < p.k_want:
+                    break
+                out.add(t)
+            out = sorted(out)
+            keep = [t for t in range(kc) if t not in out]
+            nu = len(out)
+            unlocked = V[:, out].copy()
+            nact = kact - ec  # the retained active columns follow the locked ones
+            V[:, :kc - nu + nact] = V[:, keep + list(range(kc, kc + nact))]
+            evals = evals[keep]
+            kc -= nu
+            ksub -= nu
+            n_unlocked += nu
+            history[-1]["n_unlocked"] = nu
         # step 14
         if ec:
             W[:, :kact - ec] = W[:, ec:kact]
@@ -195,20 +249,25 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
         # step 16: outer restart
         if ksub + kb > p.dim_max:
             kact = p.dim_max - 2 * kb - kc
+            if p.k_ro > 0:
+                kact = min(kact, p.k_ro)
             ksub = kc + kact
-        # step 17: next block to filter (progressive filtering)
-        parts = []
-        n_from_init = max(0, min(ec, k_init - k_i))
+            history[-1]["outer_restart"] = True
+        # step 17: next block to filter (progressive filtering), after any
+        # pairs the certificate un-locked
+        nu = unlocked.shape[1]
+        parts = [unlocked] if nu else []
+        n_from_init = max(0, min(ec, k_init - k_i, kb - nu))
         if n_from_init:
             parts.append(np.asarray(V_init[:, k_i:k_i + n_from_init], dtype=np.float64))
-        n_ritz = min(kb - ec, kact)
+        n_ritz = min(kb - ec, kact, kb - nu - n_from_init)
         if n_ritz:
             parts.append(V[:, kc:kc + n_ritz])
-        pad = kb - n_from_init - n_ritz
+        pad = kb - nu - n_from_init - n_ritz
         if pad:
             parts.append(rand_cols(pad))
         V_tmp = np.asfortranarray(np.concatenate(parts, axis=1))
-        k_i += ec
+        k_i += n_from_init
         # step 18
         if kact:
             med = _median(D_act[:kact])
@@ -217,11 +276,16 @@ def bchdav(csr, params: Params, V_init: np.ndarray | None = None) -> Result:
     k_out = min(kc, p.k_want)
     evecs = np.array(V[:, :k_out])
     ev = evals[:k_out].copy()
-    if k_out:
+    if status == "noconv" and k_out:
         R = apply_laplacian(csr, np.asfortranarray(evecs)) - evecs * ev
-        max_res = float(np.max(np.sqrt(np.sum(R * R, axis=0))))
+        cert = np.sqrt(np.sum(R * R, axis=0))
         n_other += 1
+    if k_out:
+        max_res = float(np.max(cert))
+        certified = int(np.sum(cert <= p.certify_tol))
     else:
         max_res = float("nan")
+        certified = 0
     return Result(evals=ev, evecs=evecs, converged=kc, iterations=it, n_spmm_filter=n_filter,
-                  n_spmm_other=n_other, n_random=n_random, max_residual=max_res, history=history)
+                  n_spmm_other=n_other, n_random=n_random, max_residual=max_res, history=history,
+                  certified=certified, n_unlocked=n_unlocked, status=status)

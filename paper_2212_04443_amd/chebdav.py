@@ -49,6 +49,21 @@ class ChebdavError(RuntimeError):
         self.status = status
 
 
+class IterRecord(ctypes.Structure):
+    _fields_ = [
+        ("iteration", ctypes.c_int), ("kc", ctypes.c_int), ("kact", ctypes.c_int), ("ksub", ctypes.c_int),
+        ("n_locked", ctypes.c_int), ("n_unlocked", ctypes.c_int), ("inner_restart", ctypes.c_int),
+        ("outer_restart", ctypes.c_int), ("filter_f32", ctypes.c_int), ("low_nwb", ctypes.c_double),
+        ("min_residual", ctypes.c_double), ("max_residual", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+LOG_FN = ctypes.CFUNCTYPE(None, ctypes.POINTER(IterRecord), ctypes.c_void_p)
+
+
 class Params(ctypes.Structure):
     _fields_ = [
         ("k_want", ctypes.c_int), ("kb", ctypes.c_int), ("m", ctypes.c_int), ("itmax", ctypes.c_int),
@@ -56,7 +71,8 @@ class Params(ctypes.Structure):
         ("k_ri", ctypes.c_int), ("upperb", ctypes.c_double), ("lowb", ctypes.c_double),
         ("low_nwb0", ctypes.c_double), ("filter_dtype", ctypes.c_int),
         ("f32_switch_tol", ctypes.c_double), ("seed", ctypes.c_uint64), ("timing", ctypes.c_int),
-        ("orth", ctypes.c_int),
+        ("orth", ctypes.c_int), ("k_ro", ctypes.c_int), ("refine_sweeps", ctypes.c_int),
+        ("certify_tol", ctypes.c_double), ("log_cb", LOG_FN), ("log_user", ctypes.c_void_p),
     ]
 
 
@@ -66,7 +82,8 @@ class Stats(ctypes.Structure):
         ("n_spmm_filter_f32", ctypes.c_int), ("n_spmm_other", ctypes.c_int),
         ("n_random", ctypes.c_int), ("n_replaced", ctypes.c_int), ("max_residual", ctypes.c_double),
         ("t_total_ms", ctypes.c_double), ("t_filter_ms", ctypes.c_double),
-        ("n_filter_launches", ctypes.c_int),
+        ("n_filter_launches", ctypes.c_int), ("used_fallback", ctypes.c_int), ("n_unlocked", ctypes.c_int),
+        ("n_inner_restarts", ctypes.c_int), ("n_outer_restarts", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -277,9 +294,20 @@ def tsqr(X: torch.Tensor, Q: torch.Tensor | None = None, stream=None):
 
 def make_params(k_want, kb, m, tol=1e-8, itmax=0, act_max=0, dim_max=0, k_ri=0, upperb=2.0,
                 lowb=0.0, low_nwb0=math.nan, filter_dtype=F64, f32_switch_tol=0.0, seed=0,
-                timing=False, orth="cholqr") -> Params:
-    return Params(k_want, kb, m, itmax, tol, act_max, dim_max, k_ri, upperb, lowb, low_nwb0,
-                  filter_dtype, f32_switch_tol, seed, 1 if timing else 0, _ORTH[orth])
+                timing=False, orth="cholqr", k_ro=0, refine_sweeps=0, certify_tol=0.0,
+                log=None) -> Params:
+    """chebdav_params.  `log`, if given, is a list that receives one dict per
+    Davidson iteration (chebdav_iter_record) through log_cb."""
+    cb = LOG_FN()
+    if log is not None:
+        def _cb(rec, user):
+            log.append(rec.contents.as_dict())
+        cb = LOG_FN(_cb)
+    p = Params(k_want, kb, m, itmax, tol, act_max, dim_max, k_ri, upperb, lowb, low_nwb0,
+               filter_dtype, f32_switch_tol, seed, 1 if timing else 0, _ORTH[orth], k_ro, refine_sweeps,
+               certify_tol, cb, None)
+    p._cb_ref = cb  # the callback object lives as long as the parameters
+    return p
 
 
 def solve_workspace_size(g: Graph, params: Params) -> int:

@@ -38,12 +38,19 @@ void *pinned_host(size_t bytes, int slot);
 namespace {
 
 struct Resolved {
-    int k_want, kb, m, itmax, act_max, dim_max, k_ri, lmax;
-    double tol, upperb, lowb, low_nwb0, f32_switch_tol;
+    int k_want, kb, m, itmax, act_max, dim_max, k_ri, k_ro, refine_sweeps, lmax;
+    double tol, certify_tol, upperb, lowb, low_nwb0, f32_switch_tol;
     chebdav_dtype fdt;
     chebdav_orth orth;
     uint64_t seed;
     bool timing;
+    chebdav_log_fn log_cb;
+    void *log_user;
+    // size of the active block after an outer restart (step 16) with kc locked
+    int ro_size(int kc) const {
+        const int k = dim_max - 2 * kb - kc;
+        return k_ro > 0 ? std::min(k_ro, k) : k;
+    }
 };
 
 chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
@@ -53,6 +60,11 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
     r.m = p->m;
     r.itmax = p->itmax > 0 ? p->itmax : 1000;
     r.tol = p->tol > 0 ? p->tol : 1e-8;
+    r.certify_tol = p->certify_tol > 0 ? p->certify_tol : r.tol;
+    r.k_ro = p->k_ro;
+    r.refine_sweeps = p->refine_sweeps == 0 ? 3 : std::max(0, p->refine_sweeps);
+    r.log_cb = p->log_cb;
+    r.log_user = p->log_user;
     r.act_max = p->act_max > 0 ? p->act_max : std::max(5 * r.kb, 30);
     r.dim_max = p->dim_max > 0 ? p->dim_max : std::max(r.act_max + 2 * r.kb, r.k_want + 30);
     r.k_ri = p->k_ri > 0 ? p->k_ri : std::max(r.act_max / 2, r.act_max - 3 * r.kb);
@@ -68,6 +80,9 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
     r.timing = p->timing != 0;
     r.lmax = r.k_want + r.kb;
     if (r.kb < 1 || r.k_want < 1 || r.m < 1) return fail(CHEBDAV_EINVAL, "need kb >= 1, k_want >= 1, m >= 1");
+    if (!(r.tol > 0) || !(r.certify_tol > 0) || std::isnan(p->certify_tol) || std::isnan(p->tol))
+        return fail(CHEBDAV_EINVAL, "tolerances must be positive numbers");
+    if (r.k_ro < 0) return fail(CHEBDAV_EINVAL, "k_ro < 0");
     if (r.k_want > n) return fail(CHEBDAV_EINVAL, "k_want > n");
     if (r.kb > update_max_inplace_cols()) return fail(CHEBDAV_EUNSUPPORTED, "kb > %d", update_max_inplace_cols());
     if (r.k_ri < 1 || r.k_ri > r.act_max - r.kb) return fail(CHEBDAV_EINVAL, "need 1 <= k_ri <= act_max - kb");
@@ -88,6 +103,15 @@ struct Layout {
     void *filt, *orthw, *eigw;
     size_t filt_b, orth_b, eig_b;
 };
+
+// Index-map regions (int32), the same on the device and in the pinned host
+// buffer: converged / retained active columns (act_max each), then the exit
+// certificate's order, the columns it un-locks and the locked columns it keeps
+// (k_want + kb each).
+size_t map_entries(const Resolved &r) { return (size_t)2 * r.act_max + 3 * r.lmax; }
+size_t map_cert(const Resolved &r) { return (size_t)2 * r.act_max; }
+size_t map_unl(const Resolved &r) { return (size_t)2 * r.act_max + r.lmax; }
+size_t map_keep(const Resolved &r) { return (size_t)2 * r.act_max + 2 * r.lmax; }
 
 Layout layout(Arena &a, int64_t n, const Resolved &r) {
     Layout L;
@@ -110,7 +134,7 @@ Layout layout(Arena &a, int64_t n, const Resolved &r) {
     // index maps followed by the new diagonal of H, laid out as in the pinned
     // host buffer (one host-to-device copy per iteration)
     {
-        const size_t nm = (size_t)2 * r.act_max + 2 * r.lmax;
+        const size_t nm = map_entries(r);
         char *mh = a.take<char>(sizeof(int32_t) * nm + sizeof(double) * (r.act_max + r.lmax));
         L.map = reinterpret_cast<int32_t *>(mh);
         L.hd = reinterpret_cast<double *>(mh + sizeof(int32_t) * nm);
@@ -175,9 +199,9 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
 
     // pinned host scratch: [0] Ritz values + residuals, [1] index maps / diagonal
     double *h_vals = static_cast<double *>(pinned_host(sizeof(double) * (2 * am + 2 * r.lmax + 8), 0));
-    int32_t *h_map = static_cast<int32_t *>(pinned_host(sizeof(int32_t) * (2 * am + 2 * r.lmax) + sizeof(double) * (am + r.lmax), 1));
+    int32_t *h_map = static_cast<int32_t *>(pinned_host(sizeof(int32_t) * map_entries(r) + sizeof(double) * (am + r.lmax), 1));
     if (!h_vals || !h_map) return fail(CHEBDAV_ENOMEM, "pinned host allocation failed");
-    double *h_diag = reinterpret_cast<double *>(h_map + 2 * am + 2 * r.lmax);
+    double *h_diag = reinterpret_cast<double *>(h_map + map_entries(r));
     int *h_flag = reinterpret_cast<int *>(h_vals + 2 * am + 2 * r.lmax);
 
     chebdav_stats S{};
@@ -242,10 +266,50 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         return CHEBDAV_OK;
     };
     chebdav_status result = CHEBDAV_ENOCONV;
-    int it = 0;
+    // Exit certificate (reading of step 12 with Table 1's extra SpMM): the kout
+    // smallest locked pairs, ascending, are written to evals / evecs and their
+    // fresh residuals ||A v - lambda v||_2 (one new sparse product) read back into
+    // fres; ord[t] is the locked-order column of the t-th smallest.
+    std::vector<int> ord;
+    std::vector<double> fres;
+    bool written = false;
+    auto certify = [&](int kout) -> chebdav_status {
+        CD_HIP(hipStreamSynchronize(st));  // earlier uploads from the pinned maps have completed
+        ord.resize(kc);
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return locked[x] < locked[y]; });
+        int32_t *m_cert = h_map + map_cert(r);
+        for (int t = 0; t < kout; ++t) {
+            m_cert[t] = ord[t];
+            h_diag[t] = locked[ord[t]];
+        }
+        CD_HIP(hipMemcpyAsync(L.map + map_cert(r), m_cert, sizeof(int32_t) * kout, hipMemcpyHostToDevice, st));
+        CD_HIP(hipMemcpyAsync(L.ev, h_diag, sizeof(double) * kout, hipMemcpyHostToDevice, st));
+        CD_TRY(gather_cols(L.Vl, r.lmax, evecs, r.k_want, L.map + map_cert(r), kout, n, st));
+        CD_TRY((copy_block<double, double>(L.ev, 1, evals, 1, 1, kout, st)));
+        double *tmp = L.W[1 - cur];  // free outside a rotation
+        for (int c0 = 0; c0 < kout; c0 += am) {
+            const int w = std::min(am, kout - c0);
+            CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, evecs + c0, r.k_want, nullptr, 0, tmp,
+                                                     am, w, st)));
+            CD_TRY(colnorms(tmp, am, evecs + c0, r.k_want, L.ev + c0, w, n, L.res + c0, L.part, st));
+        }
+        S.n_spmm_other += 1;
+        CD_HIP(hipMemcpyAsync(h_vals, L.res, sizeof(double) * kout, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+        fres.assign(h_vals, h_vals + kout);
+        written = true;
+        return CHEBDAV_OK;
+    };
+    int it = 0, cert_rounds = 0;
+    bool cert_failed = false;
     std::vector<double> D(am), res(kb);
     while (it < r.itmax) {
         ++it;
+        chebdav_iter_record rec{};
+        rec.iteration = it;
+        rec.low_nwb = low_nwb;
+        rec.filter_f32 = !use_f64_filter;
         double *Xnew = L.Va[cur] + kr;
         // step 5: filter
         const chebdav_dtype fdt = use_f64_filter ? CHEBDAV_F64 : CHEBDAV_F32;
@@ -297,7 +361,12 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             kact = r.k_ri;
             CD_TRY(compress(kact));
             rotated = true;
+            S.n_inner_restarts += 1;
         }
+        rec.kc = kc;
+        rec.kact = kact;
+        rec.ksub = kc + kact;
+        rec.inner_restart = rotated;
         // step 12: residuals of the first kb active pairs, from PV = B Q(:, 1:nres)
         // and PW = (A B) Q(:, 1:nres) (the rotated blocks themselves after a restart)
         const int nres = std::min(kb, kact);
@@ -331,14 +400,20 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         }
         const int ec = (int)conv.size();
         double min_open_res = INFINITY;
-        for (int i = 0; i < nres; ++i)
+        rec.min_residual = INFINITY;
+        rec.max_residual = 0.0;
+        for (int i = 0; i < nres; ++i) {
             if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
+            rec.min_residual = std::min(rec.min_residual, res[i]);
+            rec.max_residual = std::max(rec.max_residual, res[i]);
+        }
+        rec.n_locked = ec;
         // host decisions first (steps 12-16), then one upload of the maps and the new diagonal
-        const bool done = kc + ec >= r.k_want;
+        bool done = kc + ec >= r.k_want;
         int kact_next = kact - ec;
         bool outer = false;
         if (!done && kc + ec + kact_next + kb > r.dim_max) {
-            kact_next = r.dim_max - 2 * kb - (kc + ec);
+            kact_next = r.ro_size(kc + ec);
             outer = true;
         }
         int32_t *m_conv = h_map, *m_rest = h_map + am;
@@ -359,39 +434,98 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             if (!rest.empty()) CD_TRY(gather_cols(L.Q[qc], am, L.Q[qc], am, L.map + am, (int)rest.size(), kr, st));
             kact -= ec;
         }
-        // step 13
+        // step 13, with the exit certificate: pairs whose fresh residual fails are
+        // un-locked (the kb smallest first) together with the locked pairs above
+        // rank k_want - 1 that would otherwise end the loop again at once; they
+        // lead the next block to filter.
+        int nu = 0;
         if (done) {
-            result = CHEBDAV_OK;
+            CD_TRY(certify(r.k_want));
+            std::vector<int> bad;
+            for (int t = 0; t < r.k_want; ++t)
+                if (!(fres[t] <= r.certify_tol)) bad.push_back(t);
+            if (bad.empty()) {
+                result = CHEBDAV_OK;
+            } else if (cert_rounds < r.refine_sweeps) {
+                ++cert_rounds;
+                if ((int)bad.size() > kb) bad.resize(kb);
+                std::vector<char> out(kc, 0);
+                for (int t : bad) out[t] = 1;
+                for (int t = kc - 1; t >= 0 && kc - (int)std::count(out.begin(), out.end(), 1) >= r.k_want; --t) out[t] = 1;
+                std::vector<int> unl, keep;  // locked-order columns
+                for (int t = 0; t < kc; ++t) (out[t] ? unl : keep).push_back(ord[t]);
+                std::sort(keep.begin(), keep.end());
+                nu = (int)unl.size();
+                const int kc_new = kc - nu;
+                // B must hold no locked vector before the locked set shrinks: rotate
+                // it to the retained active pairs, with step 16's size for kc_new
+                kact_next = kact;
+                if (kc_new + kact + kb > r.dim_max) {
+                    kact_next = r.ro_size(kc_new);
+                    outer = true;
+                }
+                int32_t *m_unl = h_map + map_unl(r), *m_keep = h_map + map_keep(r);
+                for (int t = 0; t < nu; ++t) m_unl[t] = unl[t];
+                for (int t = 0; t < kc_new; ++t) m_keep[t] = keep[t];
+                for (int t = 0; t < kact_next; ++t) h_diag[t] = Dact[t];
+                const size_t ub = reinterpret_cast<char *>(h_diag + kact_next) - reinterpret_cast<char *>(h_map);
+                CD_HIP(hipMemcpyAsync(L.map, h_map, ub, hipMemcpyHostToDevice, st));  // certify synchronized
+                kact = kact_next;
+                CD_TRY(compress(kact));
+                CD_TRY(gather_cols(L.Vl, r.lmax, L.Vtmp, kb, L.map + map_unl(r), nu, n, st, g->dinv));
+                if (kc_new) CD_TRY(gather_cols(L.Vl, r.lmax, L.Vl, r.lmax, L.map + map_keep(r), kc_new, n, st));
+                std::vector<double> lk(kc_new);
+                for (int t = 0; t < kc_new; ++t) lk[t] = locked[keep[t]];
+                locked.swap(lk);
+                kc = kcb = kc_new;
+                S.used_fallback = 1;
+                S.n_unlocked += nu;
+                use_f64_filter = true;
+                done = false;
+                written = false;  // the next exit writes the outputs again
+            } else {
+                cert_failed = true;
+            }
+        }
+        rec.n_unlocked = nu;
+        if (done) {
+            rec.outer_restart = 0;
+            if (r.log_cb) r.log_cb(&rec, r.log_user);
             break;
         }
         // step 16: outer restart (ksub = kc + kact); B also rotated when it is full
-        if (outer) {
-            kact = kact_next;
-            CD_TRY(compress(kact));
-        } else if (kr + kb > am) {
-            CD_TRY(compress(kact));
+        if (nu == 0) {
+            if (outer) {
+                kact = kact_next;
+                CD_TRY(compress(kact));
+            } else if (kr + kb > am) {
+                CD_TRY(compress(kact));
+            }
         }
+        if (outer) S.n_outer_restarts += 1;
+        rec.outer_restart = outer;
         // step 15: H = diag of the retained non-converged Ritz values
         if (kact) CD_TRY(h_set_diag(L.H, am, L.hd, kact, st));
-        // step 17: next block = [unused V_init columns, leading Ritz vectors, random]
+        // step 17: next block = [un-locked pairs, unused V_init columns, leading Ritz vectors, random]
         {
-            const int n_init = std::max(0, std::min(ec, k_init - ki));
-            const int n_ritz = std::min(kb - ec, kact);
-            const int pad = kb - n_init - n_ritz;
-            if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, L.Vtmp, kb, n_init, n, st, g->dinv)));
+            const int n_init = std::max(0, std::min(std::min(ec, k_init - ki), kb - nu));
+            const int n_ritz = std::min(std::min(kb - ec, kact), kb - nu - n_init);
+            const int pad = kb - nu - n_init - n_ritz;
+            double *vt = L.Vtmp + nu;
+            if (n_init) CD_TRY((copy_block<double, double>(V_init + ki, k_init, vt, kb, n_init, n, st, g->dinv)));
             if (n_ritz) {
                 // the leading non-converged pairs are all among the first nres columns of PV
                 if (ec)
-                    CD_TRY(gather_cols(PV, ldp, L.Vtmp + n_init, kb, L.map + am, n_ritz, n, st, g->dinv));
+                    CD_TRY(gather_cols(PV, ldp, vt + n_init, kb, L.map + am, n_ritz, n, st, g->dinv));
                 else
-                    CD_TRY((copy_block<double, double>(PV, ldp, L.Vtmp + n_init, kb, n_ritz, n, st, g->dinv)));
+                    CD_TRY((copy_block<double, double>(PV, ldp, vt + n_init, kb, n_ritz, n, st, g->dinv)));
             }
             if (pad) {
-                CD_TRY(philox_fill(L.Vtmp + n_init + n_ritz, n, pad, kb, r.seed, next_col, st, g->dinv));
+                CD_TRY(philox_fill(vt + n_init + n_ritz, n, pad, kb, r.seed, next_col, st, g->dinv));
                 next_col += pad;
                 S.n_random += pad;
             }
-            ki += ec;
+            ki += n_init;
         }
         // step 18
         if (kact) {
@@ -400,45 +534,34 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         }
         // mixed precision: FP64 filtering once the leading open residual is small
         if (!use_f64_filter && min_open_res < r.f32_switch_tol) use_f64_filter = true;
+        if (r.log_cb) r.log_cb(&rec, r.log_user);
     }
     S.iterations = it;
-    S.converged = kc;
-    // write the k_want smallest locked pairs (or all locked ones) in ascending order
-    const int kout = std::min(kc, r.k_want);
-    CD_HIP(hipStreamSynchronize(st));  // earlier uploads from the pinned maps have completed
-    if (kout > 0) {
-        std::vector<int> ord(kc);
-        std::iota(ord.begin(), ord.end(), 0);
-        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return locked[x] < locked[y]; });
-        for (int t = 0; t < kout; ++t) {
-            h_map[t] = ord[t];
-            h_diag[t] = locked[ord[t]];
-        }
-        CD_HIP(hipMemcpyAsync(L.map, h_map, sizeof(int32_t) * kout, hipMemcpyHostToDevice, st));
-        CD_HIP(hipMemcpyAsync(L.ev, h_diag, sizeof(double) * kout, hipMemcpyHostToDevice, st));
-        CD_TRY(gather_cols(L.Vl, r.lmax, evecs, r.k_want, L.map, kout, n, st));
-        CD_TRY((copy_block<double, double>(L.ev, 1, evals, 1, 1, kout, st)));
-        // certificate: fresh residuals ||A v - lambda v|| in chunks of <= act_max columns
-        double *tmp = L.W[1 - cur];
-        for (int c0 = 0; c0 < kout; c0 += am) {
-            const int w = std::min(am, kout - c0);
-            CD_TRY((launch_cheb_step<double, double>(g, -1.0, 1.0, 0.0, evecs + c0, r.k_want, nullptr, 0, tmp,
-                                                     am, w, st)));
-            CD_TRY(colnorms(tmp, am, evecs + c0, r.k_want, L.ev + c0, w, n, L.res + c0, L.part, st));
-        }
-        S.n_spmm_other += 1;
-        CD_HIP(hipMemcpyAsync(h_vals, L.res, sizeof(double) * kout, hipMemcpyDeviceToHost, st));
-        CD_HIP(hipStreamSynchronize(st));
-        double mr = 0.0;
-        for (int t = 0; t < kout; ++t) mr = std::max(mr, h_vals[t]);
-        S.max_residual = mr;
-    } else {
-        S.max_residual = NAN;
-        CD_HIP(hipStreamSynchronize(st));
+    // outputs: the certificate of the loop's exit, or (itmax) of the locked pairs found
+    if (!written) {
+        const int kout = std::min(kc, r.k_want);
+        if (kout > 0)
+            CD_TRY(certify(kout));
+        else
+            fres.clear();
     }
+    int n_cert = 0;
+    double mr = fres.empty() ? NAN : 0.0;
+    for (double f : fres) {
+        mr = std::max(mr, f);
+        n_cert += f <= r.certify_tol;
+    }
+    S.max_residual = mr;
+    S.converged = n_cert;
+    CD_HIP(hipStreamSynchronize(st));
     S.t_total_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     if (stats) *stats = S;
-    if (result != CHEBDAV_OK) return fail(result, "itmax reached with %d of %d pairs converged", kc, r.k_want);
+    if (result != CHEBDAV_OK) {
+        if (cert_failed)
+            return fail(CHEBDAV_ENOCONV, "exit certificate failed for %d of %d pairs after %d refinement rounds",
+                        r.k_want - n_cert, r.k_want, cert_rounds);
+        return fail(result, "itmax reached with %d of %d pairs certified", n_cert, r.k_want);
+    }
     return CHEBDAV_OK;
 }
 

@@ -155,6 +155,60 @@ def test_filter_sbm200k_full_size(cd, oracle_mod, dev, dt, tol):
     assert err <= tol
 
 
+# the sparse step keeps 16 neighbour rows in flight per lane (its deep-batch
+# form) once the gathered block n x w of the element type exceeds this size
+DEEP_BYTES = 256 * 1024 * 1024
+
+
+@pytest.fixture(scope="module")
+def chunglu1m(cd, oracle_mod, dev):
+    """The Chung-Lu generator of the 8M-node workload (gamma 2.1, mean degree 16,
+    cap sqrt(N), largest component, hubs first) at 1.1M nodes: hub rows of
+    degree ~1000 beside rows of degree 1-3, and a 64-wide block larger than
+    DEEP_BYTES in FP64 and in FP32, so every step below runs the deep form."""
+    e, n = synth.chung_lu(1_100_000, seed=synth.graphs.DEFAULT_SEED + 4)
+    return cd.build_laplacian(e, n), oracle_mod.build_csr(e, n)
+
+
+@pytest.mark.parametrize("dt", [0, 1])
+def test_spmm_chung_lu_deep_matches_oracle(cd, oracle_mod, chunglu1m, dt):
+    import torch
+    g, o = chunglu1m
+    kb, es = 64, (8 if dt == 0 else 4)
+    assert o.n * kb * es > DEEP_BYTES and int(o.deg.max()) >= 500
+    rng = np.random.default_rng(11 + dt)
+    npdt = np.float64 if dt == 0 else np.float32
+    U = rng.standard_normal((o.n, kb)).astype(npdt)
+    Z = rng.standard_normal((o.n, kb)).astype(npdt)
+    Ut, Zt = torch.from_numpy(U).cuda(), torch.from_numpy(Z).cuda()
+    Yt = torch.empty_like(Ut)
+    print("case spmm chung-lu n=%d dt=%d" % (o.n, dt), flush=True)
+    AU = oracle_mod.apply_laplacian(o, U.astype(np.float64))
+    tol = 1e-14 if dt == 0 else 2e-6
+    cd.spmm(g, -1.0, 1.0, 0.0, Ut, None, Yt)
+    assert _rel_err(Yt.cpu().numpy().astype(np.float64), AU) <= tol
+    a, b, c = 0.7, -1.3, 0.25
+    cd.spmm(g, a, b, c, Ut, Zt, Yt)
+    U64, Z64 = U.astype(np.float64), Z.astype(np.float64)
+    want = a * (U64 - AU) + b * U64 + c * Z64
+    assert _rel_err(Yt.cpu().numpy().astype(np.float64), want) <= tol
+
+
+@pytest.mark.parametrize("dt,tol", [(0, 1e-12), (1, 1e-4)])
+def test_filter_chung_lu_deep_matches_oracle(cd, oracle_mod, chunglu1m, dt, tol):
+    """All three kinds of filter step (first, interior scaled, last) in the
+    deep form, on the hub-heavy graph."""
+    import torch
+    g, o = chunglu1m
+    X = np.random.default_rng(3).standard_normal((o.n, 64))
+    print("case filter chung-lu dt=%d" % dt, flush=True)
+    Y = cd.filter(g, torch.from_numpy(X).cuda(), 5, 0.3, 2.0, 0.0, dtype=dt).cpu().numpy()
+    want = oracle_mod.cheb_filter(o, X, 5, 0.3, 2.0, 0.0)
+    err = _rel_err(Y, want)
+    print("chung-lu filter dt=%d rel err %.3g" % (dt, err))
+    assert err <= tol
+
+
 def test_filter_rejects_bad_interval(cd, sbm20k):
     import torch
     g, o = sbm20k

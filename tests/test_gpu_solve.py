@@ -30,11 +30,11 @@ def _fresh_residuals(o, evals, evecs):
 o_csr_cache = [None]
 
 
-def _parity(cd, oracle_mod, edges, n, k, kb, m, seed=1, it_slack=2, **kw):
+def _parity(cd, oracle_mod, edges, n, k, kb, m, seed=1, it_slack=2, gpu_kw=None, **kw):
     o = oracle_mod.build_csr(edges, n)
     o_csr_cache[0] = o
     ref = oracle_mod.bchdav(o, oracle_mod.Params(k_want=k, kb=kb, m=m, seed=seed, **kw))
-    _, ev, V, st = _gpu_solve(cd, edges, n, k_want=k, kb=kb, m=m, seed=seed, **kw)
+    _, ev, V, st = _gpu_solve(cd, edges, n, k_want=k, kb=kb, m=m, seed=seed, **kw, **(gpu_kw or {}))
     res = _fresh_residuals(oracle_mod, ev, V)
     print("iters gpu %d oracle %d; max res %.3g; max dlam %.3g" %
           (st["iterations"], ref.iterations, res.max(), np.abs(ev - ref.evals).max()))
@@ -195,9 +195,12 @@ def test_sbm200k_full_size_parity(cd, oracle_mod, dev, form):
 
 def test_streaming_warm_start(cd, oracle_mod, dev):
     """Warm start from the eigenvectors of a slightly different graph (the
-    streaming-graph use of V_init): after 0.5% of the edges are rewired, the
-    previous eigenvectors, passed as V_init, are filtered progressively and
-    reach the new eigenpairs with fewer iterations than a random start."""
+    streaming-graph use of V_init, Alg. 2 steps 2 and 17): after 0.5% of the
+    edges are rewired, the previous eigenvectors, passed as V_init, are filtered
+    progressively and reach the new eigenpairs with fewer iterations than a
+    random start.  The oracle runs the same sequence on its own: it solves the
+    old graph, then the new one from its own previous eigenvectors; the GPU's
+    warm solve must match it to the solve bar, iterations within +-2."""
     import torch
     e, n, cfg = synth.make_config_graph("sbm200k")
     g0 = cd.build_laplacian(e, n)
@@ -210,12 +213,18 @@ def test_streaming_warm_start(cd, oracle_mod, dev):
     g1 = cd.build_laplacian(e2, n)
     rnd = cd.solve(g1, p)
     warm = cd.solve(g1, p, V_init=prev.evecs.contiguous())
+    o0 = oracle_mod.build_csr(e, n)
     o = oracle_mod.build_csr(e2, n)
+    o_prev = oracle_mod.bchdav(o0, oracle_mod.Params(k_want=32, kb=32, m=15, seed=1))
+    ref = oracle_mod.bchdav(o, oracle_mod.Params(k_want=32, kb=32, m=15, seed=1), V_init=o_prev.evecs)
     V, ev = warm.evecs.cpu().numpy(), warm.evals.cpu().numpy()
     R = oracle_mod.apply_laplacian(o, np.asfortranarray(V)) - V * ev
-    print("streaming: random start %d iterations, previous-eigenvector start %d iterations"
-          % (rnd.stats["iterations"], warm.stats["iterations"]))
+    print("streaming: random start %d iterations, previous-eigenvector start %d iterations (oracle %d)"
+          % (rnd.stats["iterations"], warm.stats["iterations"], ref.iterations))
     assert np.sqrt((R * R).sum(0)).max() <= 1e-8
+    assert np.abs(ev - ref.evals).max() <= 1e-10
+    assert sin_max_angle(ref.evecs, V) <= 1e-6
+    assert abs(warm.stats["iterations"] - ref.iterations) <= 2
     assert np.abs(ev - rnd.evals.cpu().numpy()).max() <= 1e-10
     assert warm.stats["iterations"] < rnd.stats["iterations"]
 
@@ -256,3 +265,86 @@ def test_concurrent_solves_two_threads(cd, dev):
     for i in range(2):
         assert np.array_equal(out[i][0], ref[i][0])
         assert np.array_equal(out[i][1], ref[i][1])
+
+
+def _trajectory(rows):
+    return [(r["kc"], r["kact"], r["ksub"], bool(r["inner_restart"]), bool(r["outer_restart"])) for r in rows]
+
+
+@pytest.mark.parametrize("case", ["sbm5k_16blocks", "sbm20k_64blocks"])
+def test_outer_restart_parity(cd, oracle_mod, dev, case):
+    """Alg. 2 step 16: k_want well above 2 kb + 1 makes the search space reach
+    dim_max, so the outer restart cuts it to dim_max - 2 kb - kc columns.  The
+    GPU solve matches the oracle's to the solve bar, and its per-iteration
+    trajectory (kc, kact, ksub and the restarts, from the iteration log) equals
+    the oracle's up to and including the first outer restart."""
+    if case == "sbm5k_16blocks":
+        n, B, k, kb, m, kw, seed = 5000, 16, 16, 4, 15, dict(act_max=20, dim_max=25), 1
+    else:
+        n, B, k, kb, m, kw, seed = 20_000, 64, 64, 16, 15, {}, 3
+    e, _ = synth.sbm(n, B, d_in=20, d_out=4, uneven=True, seed=seed)
+    log = []
+    print("case outer restart %s" % case, flush=True)
+    ev, V, st, ref = _parity(cd, oracle_mod, e, n, k, kb, m, seed=1, gpu_kw=dict(log=log), **kw)
+    assert sin_max_angle(ref.evecs, V) <= 1e-6
+    first = next(i for i, h in enumerate(ref.history) if h["outer_restart"])
+    assert len(log) == st["iterations"] and st["n_outer_restarts"] >= 1
+    assert _trajectory(log[:first + 1]) == _trajectory(ref.history[:first + 1])
+    print("outer restarts: gpu %d, oracle %d" % (st["n_outer_restarts"],
+                                                 sum(h["outer_restart"] for h in ref.history)))
+
+
+def test_exit_certificate_unlocks_and_refines(cd, oracle_mod, dev):
+    """The exit certificate acts: with certify_tol below tol, every pair passes
+    the in-loop test (W - V theta, tol 1e-8) but fails the fresh-product
+    certificate, so pairs are un-locked and refined until their fresh residual
+    meets certify_tol; the oracle takes the same reading."""
+    n = 1500
+    e, _ = synth.sbm(n, 4, d_in=16, d_out=3, uneven=True, seed=5)
+    o = oracle_mod.build_csr(e, n)
+    o_csr_cache[0] = o
+    lam = np.linalg.eigvalsh(oracle_mod.dense_laplacian(o))
+    ref = oracle_mod.bchdav(o, oracle_mod.Params(k_want=4, kb=4, m=11, seed=1, certify_tol=1e-13))
+    _, ev, V, st = _gpu_solve(cd, e, n, k_want=4, kb=4, m=11, seed=1, certify_tol=1e-13)
+    res = _fresh_residuals(oracle_mod, ev, V)
+    print("certificate: gpu %d iterations, %d un-locked; oracle %d iterations, %d un-locked; max res %.3g"
+          % (st["iterations"], st["n_unlocked"], ref.iterations, ref.n_unlocked, res.max()))
+    assert st["used_fallback"] == 1 and st["n_unlocked"] >= 1 and st["converged"] == 4
+    assert st["max_residual"] <= 1e-13 and res.max() <= 1.1e-13
+    assert np.abs(ev - lam[:4]).max() <= 1e-12 and np.abs(ev - ref.evals).max() <= 1e-12
+    assert abs(st["iterations"] - ref.iterations) <= 2
+    # the plain solve needs no refinement
+    _, _, _, st0 = _gpu_solve(cd, e, n, k_want=4, kb=4, m=11, seed=1)
+    assert st0["used_fallback"] == 0 and st0["n_unlocked"] == 0 and st0["max_residual"] <= 1e-8
+
+
+def test_exit_certificate_failure_is_noconv(cd, dev):
+    """A certificate no pair can meet ends the solve with ENOCONV after
+    refine_sweeps rounds; the pairs are still written and stats.converged counts
+    only the certified ones."""
+    n = 1500
+    e, _ = synth.sbm(n, 4, d_in=16, d_out=3, uneven=True, seed=5)
+    g = cd.build_laplacian(e, n)
+    r = cd.solve(g, cd.make_params(k_want=4, kb=4, m=11, seed=1, certify_tol=1e-30, refine_sweeps=2),
+                 allow_noconv=True)
+    assert r.status == cd.ENOCONV
+    assert r.stats["converged"] < 4 and r.stats["used_fallback"] == 1
+    assert r.stats["n_unlocked"] >= 2 and np.isfinite(r.evals.cpu().numpy()).all()
+
+
+@pytest.mark.slow
+def test_chung_lu_500k_oracle_parity(cd, oracle_mod, dev):
+    """A full solve on a Chung-Lu graph from the 8M-node workload's generator at
+    500k nodes (hub rows of degree ~800, no planted clusters), k = kb = 32,
+    m = 20, against the oracle's full solve.  Eigenvalues are pinned at 1e-10 by
+    the residual bound (Kato-Temple).  The graph has no planted clusters: the
+    gap after the 32nd eigenvalue is only 2.3e-3 (the oracle's 36 smallest:
+    0.234955 then 0.237232), so Davis-Kahan bounds each solution's angle to the
+    exact subspace by sqrt(32) 1e-8 / 2.3e-3 = 2.5e-5, and the two solutions'
+    largest principal angle by twice that."""
+    e, n = synth.chung_lu(500_000, seed=synth.graphs.DEFAULT_SEED + 4)
+    print("case chung-lu 500k full solve (n=%d)" % n, flush=True)
+    ev, V, st, ref = _parity(cd, oracle_mod, e, n, 32, 32, 20, seed=1)
+    ang = sin_max_angle(ref.evecs, V)
+    print("chung-lu 500k: largest principal angle %.3g" % ang)
+    assert ang <= 1e-4

@@ -150,3 +150,51 @@ def test_parameter_defaults(oracle_mod):
     assert p.low_nwb0 == pytest.approx(2 * 4 / 5000)
     with pytest.raises(ValueError):
         oracle_mod.resolve_params(oracle_mod.Params(k_want=100, kb=4, m=5, dim_max=60), 5000)
+
+
+@pytest.mark.parametrize("k_ro", [0, 5])
+def test_outer_restart_against_dense(oracle_mod, k_ro):
+    """Alg. 2 step 16 fires (k_want = 12 > 2 kb + 1 with a small dim_max): the
+    search space is cut to dim_max - 2 kb - kc columns (or k_ro), and the result
+    still equals the dense eigendecomposition."""
+    n = 1800
+    e, _ = synth.sbm(n, 12, d_in=20, d_out=4, uneven=True, seed=1)
+    g = oracle_mod.build_csr(e, n)
+    p = oracle_mod.Params(k_want=12, kb=3, m=11, seed=1, act_max=15, dim_max=21, k_ro=k_ro)
+    r = oracle_mod.bchdav(g, p)
+    _check_common(oracle_mod, g, r, 12)
+    lam = np.linalg.eigvalsh(oracle_mod.dense_laplacian(g))
+    assert np.abs(r.evals - lam[:12]).max() <= 1e-10
+    h = r.history
+    fired = [i for i, x in enumerate(h) if x["outer_restart"]]
+    assert fired
+    for i in fired:
+        kc_after = h[i]["kc"] + h[i]["ec"] - h[i]["n_unlocked"]
+        ro = 21 - 2 * 3 - kc_after
+        if k_ro:
+            ro = min(ro, k_ro)
+        # the next iteration starts from the cut active block plus one new block
+        assert h[i + 1]["kact"] == ro + 3 and h[i + 1]["kc"] == kc_after
+        assert h[i]["ksub"] - h[i]["n_unlocked"] + 3 > 21
+
+
+def test_exit_certificate_unlocks_and_refines(oracle_mod):
+    """Exit certificate (fresh residuals of the returned pairs): with a stricter
+    certificate tolerance than the loop's, the pairs that fail it are un-locked
+    and filtered again until every fresh residual meets it."""
+    n = 1500
+    e, _ = synth.sbm(n, 4, d_in=16, d_out=3, uneven=True, seed=5)
+    g = oracle_mod.build_csr(e, n)
+    lam = np.linalg.eigvalsh(oracle_mod.dense_laplacian(g))
+    plain = oracle_mod.bchdav(g, oracle_mod.Params(k_want=4, kb=4, m=11, seed=1))
+    r = oracle_mod.bchdav(g, oracle_mod.Params(k_want=4, kb=4, m=11, seed=1, certify_tol=1e-13))
+    assert plain.n_unlocked == 0 and plain.max_residual > 1e-13
+    assert r.status == "ok" and r.n_unlocked > 0 and r.iterations > plain.iterations
+    R = oracle_mod.apply_laplacian(g, np.asfortranarray(r.evecs)) - r.evecs * r.evals
+    assert np.sqrt((R * R).sum(0)).max() <= 1e-13
+    assert np.abs(r.evals - lam[:4]).max() <= 1e-12
+    # a certificate that cannot be met ends unconverged after refine_sweeps rounds
+    bad = oracle_mod.bchdav(g, oracle_mod.Params(k_want=4, kb=4, m=11, seed=1, certify_tol=1e-30,
+                                                 refine_sweeps=2))
+    assert bad.status == "certificate" and bad.certified < 4
+    assert sum(1 for x in bad.history if x["n_unlocked"]) == 2
