@@ -2,19 +2,23 @@
 """Benchmark: time to the k smallest eigenpairs of the normalized Laplacian at
 residual 1e-8, on one MI355X.
 
-Workload (default): SBM graph, N = 200,000 nodes in 32 blocks of uneven size
-(size_i proportional to 1 + U(0,1)), expected intra-block degree 20 and
-inter-block degree 4 (about 4.8M stored nonzeros), seeded; k = kb = 32, filter
-degree m = 15.  The plain FP64 path is the primary figure; the FP32-filter form
-(FP64 orthonormalization, Rayleigh-Ritz and residuals, FP64 filter once the
-leading residual is small) is timed beside it.
+Workload (default): Chung-Lu power-law graph, N = 8,000,000 expected-degree
+weights w_i proportional to (i+1)^(-1/(gamma-1)), gamma = 2.1, mean degree 16,
+capped at sqrt(N), largest connected component kept (7.86M nodes, 127.9M
+stored nonzeros, hubs first), seeded; k = kb = 64, filter degree m = 20.  It
+stands in for the skewed MAWI / Graph500 matrices of the paper's experiments.
+The plain FP64 path from a random start is the primary figure; the FP32-filter
+form and the FP32-filter form started from the trained network are timed
+beside it (fewer repetitions).  Other workloads: --workload sbm200k, sbm2m,
+sbm1m, sbm5k.
 
-One step = one complete chebdav_solve (random start -> k converged pairs with
-fresh FP64 residual certificate) on the graph already resident in HBM; the
-graph build is timed separately and excluded.  The roofline figure is the fused
-Chebyshev sparse step, timed live with HIP events on the solve's stream over
-the timed region.  The CPU baseline is the FP64 oracle solving the same graph
-on the host's cores.
+One step = one complete chebdav_solve (random start -> k pairs whose fresh FP64
+residual certificate is <= 1e-8) on the graph already resident in HBM; the
+graph build (host edge upload included) is timed separately and excluded.
+The roofline figure is the fused Chebyshev sparse step (k_cheb_step), timed
+live with HIP events on the solve's stream around every filter in the timed
+solves.  The CPU baseline is the FP64 oracle on a bounded sample of the same
+workload (stated in the line), on the host's cores.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
 """
@@ -24,6 +28,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -31,6 +36,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+INFINITY_CACHE_BYTES = 256 * 1024 * 1024
 METRIC = "time to k eigenpairs at residual 1e-8 (s); Chebyshev-filter SpMM HBM GB/s"
 
 
@@ -49,87 +55,117 @@ def flops_per_step(n, nnz, kb):
     return 2 * nnz * kb + 5 * n * kb
 
 
-def run_forms(cd, torch, g, cfg, forms, steps, warmup, seed):
-    out = {}
-    for form in forms:
-        dt = cd.F32 if form == "f32" else cd.F64
-        orth = "tsqr" if form == "f64_tsqr" else "cholqr"
-        p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed,
-                           filter_dtype=dt, timing=True, orth=orth)
-        ws = torch.empty(cd.solve_workspace_size(g, p), dtype=torch.uint8, device="cuda")
-        for _ in range(warmup):
-            cd.solve(g, p, workspace=ws)
-        torch.cuda.synchronize()
-        stats = []
-        t0 = time.perf_counter()
-        for i in range(steps):
-            r = cd.solve(g, p, workspace=ws)
-            stats.append(r.stats)
-        torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / steps
-        st = stats[-1]
-        tf = sum(s["t_filter_ms"] for s in stats)
-        nl = sum(s["n_filter_launches"] for s in stats)
-        out[form] = dict(seconds=t, iterations=st["iterations"], n_spmm_filter=st["n_spmm_filter"],
-                         n_spmm_filter_f32=st["n_spmm_filter_f32"], n_spmm_other=st["n_spmm_other"],
-                         max_residual=st["max_residual"], filter_ms_per_launch=tf / max(nl, 1),
-                         filter_ms_per_solve=tf / steps, evals=r.evals.cpu().numpy(), evecs=r.evecs)
-        log("form %s: %.2f ms/solve, %d iterations, filter %.3f ms/solve (%.1f us/step), max res %.2e"
-            % (form, 1e3 * t, st["iterations"], tf / steps, 1e3 * tf / max(nl, 1), st["max_residual"]))
-        del ws
-        torch.cuda.empty_cache()
-    return out
+def step_kernel_name(n, kb, s, scaled=True):
+    """Template instance of k_cheb_step the library launches for an n x kb block
+    of s-byte elements with leading dimension kb (the rule of its launcher: 16
+    bytes per lane when kb s is a multiple of 16, else one element per lane; G
+    lanes per row rounded up to a power of two; deep batches once
+    n kb s > 256 MiB)."""
+    ve = 16 // s
+    if kb % ve:            # widths not a multiple of 16 bytes take the scalar path
+        ve = 1
+    lanes = -(-min(kb, 64 * ve) // ve)
+    G = 1
+    while G < lanes:
+        G <<= 1
+    deep = G >= 8 and n * kb * s > INFINITY_CACHE_BYTES
+    t = "double" if s == 8 else "float"
+    return "k_cheb_step<%s, %s, %d, %d, %s, %s>" % (t, t, ve, G, "false" if scaled else "true",
+                                                    "true" if deep else "false")
 
 
-def warm_start_form(cd, torch, g, cfg, steps, seed, filter_dtype):
-    """Solve started from the trained network (inference + Rayleigh-Ritz included)."""
-    from paper_2212_04443_amd import gcn
-    if not os.path.exists(gcn.WEIGHTS_FILE):
-        return None
-    net = gcn.Net.load()
-    p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed, filter_dtype=filter_dtype)
-    ws = torch.empty(cd.solve_workspace_size(g, p), dtype=torch.uint8, device="cuda")
-    V0, _ = gcn.warm_start(g, net, seed=seed)
-    cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        V0, _ = gcn.warm_start(g, net, seed=seed)
-        r = cd.solve(g, p, V_init=V0.contiguous(), workspace=ws)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
-    name = "gcn_warm_" + ("f64" if filter_dtype == cd.F64 else "f32")
-    log("form %s: %.2f ms/solve (inference included), %d iterations" % (name, 1e3 * t, r.stats["iterations"]))
-    out = dict(seconds=t, iterations=r.stats["iterations"], n_spmm_filter=r.stats["n_spmm_filter"],
-               max_residual=r.stats["max_residual"], evals=r.evals.cpu().numpy())
-    del ws, V0, r
-    torch.cuda.empty_cache()
-    return name, out
+FORMS = {
+    # name: (filter dtype, orthonormalization, start)
+    "f64": ("f64", "cholqr", "random"),
+    "f32": ("f32", "cholqr", "random"),
+    "f64_tsqr": ("f64", "tsqr", "random"),
+    "gcn_f64": ("f64", "cholqr", "gcn"),
+    "gcn_f32": ("f32", "cholqr", "gcn"),
+    "f64_lanczos": ("f64", "cholqr", "lanczos"),
+}
 
 
-def lanczos_form(cd, torch, g, cfg, steps, seed, lanczos_steps=10):
-    """FP64 solve with the filter's upper bound from a Lanczos estimate (Sec. 2)
-    instead of the analytic 2; the estimate is part of the timed work."""
-    def once():
-        _, hi, _, _ = cd.lanczos_bounds(g, lanczos_steps, seed=seed)
-        p = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed, upperb=min(hi, 2.0))
-        return hi, cd.solve(g, p, workspace=ws)
-    p0 = cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed)
+def run_form(cd, torch, g, cfg, form, steps, warmup, seed, net=None):
+    """Times `steps` complete solves after `warmup` untimed ones.  GCN forms
+    include feature generation, inference and Rayleigh-Ritz of the network
+    output in every timed solve; the Lanczos form includes its 10-step bound
+    estimate."""
+    fdt, orth, start = FORMS[form]
+    dt = cd.F32 if fdt == "f32" else cd.F64
+
+    def params(upperb=2.0):
+        return cd.make_params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], tol=1e-8, seed=seed, filter_dtype=dt,
+                              timing=True, orth=orth, upperb=upperb)
+
+    p0 = params()
     ws = torch.empty(cd.solve_workspace_size(g, p0), dtype=torch.uint8, device="cuda")
-    once()
+    extra = {}
+
+    def once():
+        if start == "gcn":
+            from paper_2212_04443_amd import gcn
+            V0, _ = gcn.warm_start(g, net, seed=seed)
+            return cd.solve(g, p0, V_init=V0.contiguous(), workspace=ws)
+        if start == "lanczos":
+            _, hi, _, _ = cd.lanczos_bounds(g, 10, seed=seed)
+            extra["upper_bound"] = hi
+            return cd.solve(g, params(min(hi, 2.0)), workspace=ws)
+        return cd.solve(g, p0, workspace=ws)
+
+    for _ in range(warmup):
+        once()
     torch.cuda.synchronize()
+    stats = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        hi, r = once()
+        r = once()
+        stats.append(r.stats)
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
-    log("form f64_lanczos_upper: %.2f ms/solve (estimate included), upper bound %.4f, %d iterations"
-        % (1e3 * t, hi, r.stats["iterations"]))
-    out = dict(seconds=t, iterations=r.stats["iterations"], n_spmm_filter=r.stats["n_spmm_filter"],
-               max_residual=r.stats["max_residual"], upper_bound=hi, evals=r.evals.cpu().numpy())
-    del ws, r
-    torch.cuda.empty_cache()
-    return out
+    st = stats[-1]
+    tf = sum(s["t_filter_ms"] for s in stats)
+    nl = sum(s["n_filter_launches"] for s in stats)
+    rec = dict(seconds=t, steps=steps, warmup=warmup, iterations=st["iterations"],
+               n_spmm_filter=st["n_spmm_filter"], n_spmm_filter_f32=st["n_spmm_filter_f32"],
+               n_spmm_other=st["n_spmm_other"], max_residual=st["max_residual"],
+               used_fallback=st["used_fallback"], filter_ms_per_launch=tf / max(nl, 1),
+               filter_ms_per_solve=tf / steps, **extra)
+    log("form %s: %.2f ms/solve over %d, %d iterations, filter %.2f ms/solve (%.1f us/step), max res %.2e"
+        % (form, 1e3 * t, steps, st["iterations"], tf / steps, 1e3 * tf / max(nl, 1), st["max_residual"]))
+    evals, evecs = r.evals.cpu().numpy(), r.evecs
+    del ws
+    return rec, evals, evecs
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a plain
+    1 GiB copy), or None if the kernel source changed since it was taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "k_cheb_step_%s_traffic.json" % workload)
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    src = open(os.path.join(ROOT, "paper_2212_04443_amd", "csrc", "spmm.hip"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k["traffic_bytes_per_launch"]
+
+
+def load_imbalance(cd, g):
+    """The paper's load-imbalance measure p * max_w nnz(w) / nnz (Table 2) over
+    the eight per-XCD row ranges the sparse step uses, and over eight ranges of
+    equal row count for comparison."""
+    import numpy as np
+    rp = cd.graph_export(g)[0].cpu().numpy()
+    b = cd.graph_row_split(g)
+    per = np.diff(rp[b])
+    eq = np.linspace(0, g.n, 9).round().astype(np.int64)
+    per_eq = np.diff(rp[eq])
+    return dict(parts=8, xcd_ranges=float(8 * per.max() / max(g.nnz, 1)),
+                equal_rows=float(8 * per_eq.max() / max(g.nnz, 1)),
+                xcd_nnz=[int(x) for x in per], xcd_rows=[int(x) for x in np.diff(b)])
 
 
 def streaming_form(cd, torch, edges, n, cfg, prev_evecs, steps, seed, frac=0.005):
@@ -146,6 +182,7 @@ def streaming_form(cd, torch, edges, n, cfg, prev_evecs, steps, seed, frac=0.005
     ws = torch.empty(cd.solve_workspace_size(g1, p), dtype=torch.uint8, device="cuda")
     V0 = prev_evecs.contiguous()
     rec = {"rewired_fraction": frac}
+    ev = {}
     for name, vi in (("random_start", None), ("previous_eigenvectors", V0)):
         cd.solve(g1, p, V_init=vi, workspace=ws)
         torch.cuda.synchronize()
@@ -155,8 +192,8 @@ def streaming_form(cd, torch, edges, n, cfg, prev_evecs, steps, seed, frac=0.005
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / steps
         rec[name] = dict(seconds=t, iterations=r.stats["iterations"], max_residual=r.stats["max_residual"])
-        rec[name + "_evals"] = r.evals.cpu().numpy()
-    rec["max_dlambda"] = float(np.abs(rec.pop("random_start_evals") - rec.pop("previous_eigenvectors_evals")).max())
+        ev[name] = r.evals.cpu().numpy()
+    rec["max_dlambda"] = float(np.abs(ev["random_start"] - ev["previous_eigenvectors"]).max())
     log("streaming warm start (%.1f %% of edges rewired): random start %.2f ms, %d iterations; "
         "previous eigenvectors %.2f ms, %d iterations" % (100 * frac, 1e3 * rec["random_start"]["seconds"],
         rec["random_start"]["iterations"], 1e3 * rec["previous_eigenvectors"]["seconds"],
@@ -166,34 +203,16 @@ def streaming_form(cd, torch, edges, n, cfg, prev_evecs, steps, seed, frac=0.005
     return rec
 
 
-def per_pair_report(cd, torch, g, res, ref_evals):
-    """Per eigenpair, for every timed form: |lambda - lambda_oracle| against the FP64
-    oracle's eigenvalues and the fresh FP64 residual ||A v - lambda v||_2 (A v by
-    the library's own sparse step)."""
-    import numpy as np
-    out = {"oracle_evals": [float(x) for x in ref_evals]}
-    for form, r in res.items():
-        V = r["evecs"]
-        Y = torch.empty_like(V)
-        cd.spmm(g, -1.0, 1.0, 0.0, V, None, Y)
-        lam = torch.from_numpy(np.asarray(r["evals"])).to(V.device)
-        resid = torch.linalg.vector_norm(Y - V * lam, dim=0).cpu().numpy()
-        out[form] = {"dlambda": [float(x) for x in np.abs(np.asarray(r["evals"]) - ref_evals)],
-                     "residual": [float(x) for x in resid]}
-        log("form %s vs oracle: max |dlambda| %.2e, max residual %.2e over %d pairs"
-            % (form, max(out[form]["dlambda"]), float(resid.max()), len(resid)))
-    return out
-
-
 def cluster_tail(cd, evecs, truth, k, seed):
     """Clustering tail (row normalization + K-means) on the FP64 eigenvectors,
     scored against the planted blocks."""
+    import torch
     from paper_2212_04443_amd import spectral
     cd.cluster(evecs, k, seed=seed)
-    torch_sync()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     labels, _, rounds, inertia = cd.cluster(evecs, k, seed=seed)
-    torch_sync()
+    torch.cuda.synchronize()
     t = time.perf_counter() - t0
     lab = labels.cpu().numpy()
     rec = dict(ms=1e3 * t, rounds=rounds, inertia=inertia)
@@ -203,31 +222,6 @@ def cluster_tail(cd, evecs, truth, k, seed):
     log("clustering tail: %.2f ms, %d rounds%s" % (rec["ms"], rounds,
         ", ARI %.4f NMI %.4f" % (rec["ari"], rec["nmi"]) if truth is not None else ""))
     return rec
-
-
-def torch_sync():
-    import torch
-    torch.cuda.synchronize()
-
-
-def measured_traffic(workload, kb, n):
-    """HBM bytes per FP64 k_cheb_step launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the reading for a plain
-    1 GiB copy), or None if the kernel source changed since it was taken."""
-    import hashlib
-    f = os.path.join(ROOT, "profiles", "k_cheb_step_%s_traffic.json" % workload)
-    if not os.path.exists(f):
-        return None
-    rec = json.load(open(f))
-    src = open(os.path.join(ROOT, "paper_2212_04443_amd", "csrc", "spmm.hip"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
-        return None
-    # the filter's interior steps (scaled variables) dominate: m - 1 of its m launches;
-    # the library takes deep batches once the gathered block exceeds 256 MiB
-    deep = kb >= 16 and n * kb * 8 > 256 * 1024 * 1024
-    k = rec.get("kernels", {}).get("k_cheb_step<double, double, 2, %d, false, %s>"
-                                   % (kb * 8 // 16, "true" if deep else "false"))
-    return None if k is None else k["traffic_bytes_per_launch"]
 
 
 def copy_calibration():
@@ -248,24 +242,97 @@ def describe(name, n, nnz, cfg):
         shape += ("d_in=%g, d_out=%g" % (cfg["d_in"], cfg["d_out"]) if "d_in" in cfg
                   else "p_in=%g, p_out=%g" % (cfg["p_in"], cfg["p_out"]))
     else:
-        shape = "Chung-Lu n=%d (largest component), gamma=%g, mean degree %g" % (n, cfg["gamma"], cfg["mean_degree"])
+        shape = ("Chung-Lu n=%d (largest component of %d), gamma=%g, mean degree %g, cap sqrt(N)"
+                 % (n, cfg["n"], cfg["gamma"], cfg["mean_degree"]))
     return "%s: %s, nnz=%d; k=kb=%d, m=%d, tol=1e-8" % (name, shape, nnz, cfg["k"], cfg["m"])
 
 
-def cpu_baseline(edges, n, cfg, seed, reps=3):
-    """The FP64 oracle's complete solve of the same graph, median of `reps` runs."""
+# ---------------------------------------------------------------------------
+# CPU baseline (the oracle; test infrastructure, used only here)
+# ---------------------------------------------------------------------------
+def cpu_baseline(cd, torch, g, edges, n, cfg, seed, full_solve):
+    """The FP64 oracle on the host's cores.  Small workloads (full_solve): its
+    complete solve, median of 3.  Large ones: a bounded sample, the Chebyshev
+    filter of Alg. 3 with degree 2 on one n x kb block (two sparse steps and the
+    recurrence), beside the GPU's time for the same call."""
     import numpy as np
     import oracle
     oracle.build(force=False)
-    g = oracle.build_csr(edges, n)
-    times = []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        r = oracle.bchdav(g, oracle.Params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], seed=seed))
-        times.append(time.perf_counter() - t0)
-    return dict(value=float(np.median(times)), unit="s", cores=oracle.num_threads(), kind="oracle",
-                sample="complete FP64 oracle solve of the same workload, median of %d runs "
-                       "(%d iterations, max residual %.1e)" % (reps, r.iterations, r.max_residual)), r
+    t0 = time.perf_counter()
+    o = oracle.build_csr(edges, n)
+    log("oracle CSR built in %.1f s" % (time.perf_counter() - t0))
+    if full_solve:
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            r = oracle.bchdav(o, oracle.Params(k_want=cfg["k"], kb=cfg["kb"], m=cfg["m"], seed=seed))
+            times.append(time.perf_counter() - t0)
+        cb = dict(value=float(np.median(times)), unit="s", cores=oracle.num_threads(), kind="oracle",
+                  sample="complete FP64 oracle solve of the same workload, median of 3 runs "
+                         "(%d iterations, max residual %.1e)" % (r.iterations, r.max_residual))
+        return cb, o, r
+    X = np.random.default_rng(seed).standard_normal((n, cfg["kb"]))
+    cut = 2.0 * cfg["k"] / n
+    t0 = time.perf_counter()
+    Y = oracle.cheb_filter(o, X, 2, cut, 2.0, 0.0)
+    t_cpu = time.perf_counter() - t0
+    Xt = torch.from_numpy(X).cuda()
+    Yg = cd.filter(g, Xt, 2, cut, 2.0, 0.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        Yg = cd.filter(g, Xt, 2, cut, 2.0, 0.0)
+    torch.cuda.synchronize()
+    t_gpu = (time.perf_counter() - t0) / 5
+    err = float(np.abs(Yg.cpu().numpy() - Y).max() / np.abs(Y).max())
+    cb = dict(value=t_cpu, unit="s", cores=oracle.num_threads(), kind="oracle",
+              sample="FP64 oracle Chebyshev filter of degree 2 (Alg. 3: two sparse steps and the recurrence) "
+                     "on one %d x %d block of the same graph; a complete oracle solve of this workload takes "
+                     "hours and about 60 GB" % (n, cfg["kb"]),
+              gpu_same_sample_s=t_gpu, gpu_vs_oracle_rel_err=err)
+    log("oracle sample: %.2f s on %d threads; GPU %.2f ms for the same filter (rel err %.1e)"
+        % (t_cpu, cb["cores"], 1e3 * t_gpu, err))
+    return cb, o, None
+
+
+def oracle_one_thread_c1(seed):
+    """The oracle's complete FP64 solve of the 5000-node SBM on one host thread
+    (OpenMP and BLAS both single-threaded), in a child process."""
+    code = ("import sys, time, json; sys.path.insert(0, %r); import oracle, synth; oracle.build(force=False); "
+            "e, n, c = synth.make_config_graph('sbm5k'); o = oracle.build_csr(e, n); ts = []\n"
+            "for _ in range(3):\n"
+            "    t = time.perf_counter(); r = oracle.bchdav(o, oracle.Params(k_want=4, kb=4, m=11, seed=%d)); "
+            "ts.append(time.perf_counter() - t)\n"
+            "print(json.dumps(dict(seconds=sorted(ts)[1], iterations=r.iterations, threads=oracle.num_threads())))"
+            % (ROOT, seed))
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    if out.returncode != 0:
+        return {"error": out.stderr[-300:]}
+    return json.loads(out.stdout.strip().splitlines()[-1])
+
+
+def per_pair_report(o, res, ref_evals):
+    """Per eigenpair and timed form: the fresh FP64 residual ||A v - lambda v||_2
+    with A v by the oracle's own sparse product, and |lambda - lambda_ref|
+    against the oracle's eigenvalues when it solved the workload, otherwise
+    against the primary GPU form's."""
+    import numpy as np
+    import oracle
+    out = {"reference": "oracle" if ref_evals is not None else "primary form"}
+    if ref_evals is None:
+        ref_evals = next(iter(res.values()))["evals"]
+    out["reference_evals"] = [float(x) for x in ref_evals]
+    for form, r in res.items():
+        V = r["evecs"].cpu().numpy()
+        lam = np.asarray(r["evals"])
+        R = oracle.apply_laplacian(o, np.asfortranarray(V)) - V * lam
+        resid = np.sqrt((R * R).sum(0))
+        out[form] = {"dlambda": [float(x) for x in np.abs(lam - ref_evals)],
+                     "residual": [float(x) for x in resid]}
+        log("form %s: max |dlambda| %.2e (vs %s), max fresh residual by the oracle %.2e over %d pairs"
+            % (form, max(out[form]["dlambda"]), out["reference"], float(resid.max()), len(resid)))
+    return out
 
 
 def main():
@@ -273,17 +340,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="sbm200k")
-    ap.add_argument("--forms", default="f64,f32,f64_tsqr",
-                    help="comma list of f64, f32 (FP32 filter), f64_tsqr (Householder TSQR in place of "
-                         "Cholesky QR); the first is primary")
+    ap.add_argument("--workload", default="chunglu8m")
+    ap.add_argument("--forms", default="f64,f32,gcn_f32",
+                    help="comma list of %s; the first is primary" % ", ".join(FORMS))
+    ap.add_argument("--other-steps", type=int, default=3,
+                    help="timed solves of each non-primary form (at most --steps), after one warm-up")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-warm-start", action="store_true", help="skip the GCN warm-start forms")
-    ap.add_argument("--no-cluster", action="store_true", help="skip the clustering tail")
-    ap.add_argument("--no-lanczos", action="store_true", help="skip the form with a Lanczos upper bound")
-    ap.add_argument("--no-streaming", action="store_true",
-                    help="skip the streaming-graph warm start (rewired graph, previous eigenvectors as V_init)")
+    ap.add_argument("--cluster", action="store_true", help="also time the clustering tail (SBM workloads)")
+    ap.add_argument("--streaming", action="store_true",
+                    help="also time the streaming-graph warm start (rewired graph, previous eigenvectors as V_init)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -291,7 +357,7 @@ def main():
         copy_calibration()
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path "
+        print("bench.py measures one GPU only: libchebdav has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
@@ -311,7 +377,8 @@ def main():
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     edges, n, cfg = synth.make_config_graph(args.workload)
-    log("generated %s: n=%d, %d edges in %.1f s" % (args.workload, n, len(edges), time.perf_counter() - t0))
+    t_gen = time.perf_counter() - t0
+    log("generated %s: n=%d, %d edges in %.1f s" % (args.workload, n, len(edges), t_gen))
     torch.cuda.synchronize()
     tb = time.perf_counter()
     g = cd.build_laplacian(edges, n)
@@ -326,15 +393,36 @@ def main():
     del g2
     log("graph built on the GPU: nnz=%d, max degree %d, %.1f ms first build, %.1f ms rebuild "
         "(host edge upload included)" % (g.nnz, g.max_deg, 1e3 * t_build, 1e3 * t_rebuild))
+    imb = load_imbalance(cd, g)
+    log("load imbalance p max nnz / nnz over 8 ranges: %.3f (XCD ranges), %.3f (equal row counts)"
+        % (imb["xcd_ranges"], imb["equal_rows"]))
 
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    res = run_forms(cd, torch, g, cfg, forms, args.steps, args.warmup, args.seed)
-    prim = res[forms[0]]
+    for f in forms:
+        if f not in FORMS:
+            ap.error("unknown form %s" % f)
+    net = None
+    if any(FORMS[f][2] == "gcn" for f in forms):
+        from paper_2212_04443_amd import gcn
+        net = gcn.Net.load()
+    res = {}
+    for i, f in enumerate(forms):
+        steps = args.steps if i == 0 else max(1, min(args.steps, args.other_steps))
+        warm = args.warmup if i == 0 else 1
+        rec, ev, V = run_form(cd, torch, g, cfg, f, steps, warm, args.seed, net)
+        res[f] = dict(rec=rec, evals=ev, evecs=V)
+        if i > 0:
+            rec["max_dlambda_vs_primary"] = float(np.abs(ev - res[forms[0]]["evals"]).max())
+        torch.cuda.empty_cache()
+    prim = res[forms[0]]["rec"]
     kb = cfg["kb"]
-    s = 8 if forms[0] == "f64" else 4
-    bstep = bytes_per_step(n, g.nnz, kb, 8)     # FP64 steps (the primary path)
-    achieved = bstep / (prim["filter_ms_per_launch"] * 1e-3) / 1e9
-    traffic = measured_traffic(args.workload, kb, n) if forms[0] == "f64" else None
+    # the primary form's filter steps: FP64 unless the primary is an FP32-filter form
+    s = 4 if FORMS[forms[0]][0] == "f32" else 8
+    bstep = bytes_per_step(n, g.nnz, kb, s)
+    t_launch = prim["filter_ms_per_launch"] * 1e-3
+    achieved = bstep / t_launch / 1e9
+    kname = step_kernel_name(n, kb, s)
+    traffic = measured_traffic(args.workload, kname) if s == 8 else None
     line = {
         "metric": METRIC,
         "value": prim["seconds"],
@@ -346,61 +434,55 @@ def main():
         "higher_is_better": False,
         "scaling": "strong",
         "vs_baseline": None,
-        "dtype": "f32+f64" if forms[0] == "f32" else "f64",
+        "dtype": "f32+f64" if s == 4 else "f64",
         "data": "synthetic",
         "config": {
             "workload": describe(args.workload, n, g.nnz, cfg),
             "form": forms[0],
+            "start": FORMS[forms[0]][2],
             "seed": args.seed,
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_cheb_step (fused D^-1/2 S D^-1/2 SpMM + Chebyshev axpby), FP64",
+            "kernel": kname + " (fused D^-1/2 S D^-1/2 SpMM + Chebyshev axpby)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
             "bytes_per_launch": bstep,
-            "avg_launch_us": 1e3 * prim["filter_ms_per_launch"],
-            "traffic_gbs": None if traffic is None else traffic / (prim["filter_ms_per_launch"] * 1e-3) / 1e9,
+            "avg_launch_us": 1e6 * t_launch,
+            "traffic_gbs": None if traffic is None else traffic / t_launch / 1e9,
+            "traffic_over_algorithmic": None if traffic is None else traffic / bstep,
+            "gathered_block_bytes": n * kb * s,
+            "block_fits_infinity_cache": n * kb * s <= INFINITY_CACHE_BYTES,
         },
         "iterations": prim["iterations"],
         "n_spmm_filter": prim["n_spmm_filter"],
         "max_residual": prim["max_residual"],
-        "filter_gflops": flops_per_step(n, g.nnz, kb) / (prim["filter_ms_per_launch"] * 1e-3) / 1e9,
+        "filter_gflops": flops_per_step(n, g.nnz, kb) / t_launch / 1e9,
+        "graph_generation_s": t_gen,
         "graph_build_ms": 1e3 * t_build,
         "graph_rebuild_ms": 1e3 * t_rebuild,
-        "forms": {f: {k: v for k, v in r.items() if k not in ("evals", "evecs")} for f, r in res.items()},
+        "load_imbalance": imb,
+        "forms": {f: r["rec"] for f, r in res.items()},
     }
-    if len(forms) > 1:
-        a, b2 = res[forms[0]]["evals"], res[forms[1]]["evals"]
-        line["forms_max_dlambda"] = float(np.abs(a - b2).max())
-        for f in forms[2:]:
-            line[f + "_max_dlambda"] = float(np.abs(res[f]["evals"] - a).max())
-    for fdt in ([cd.F64, cd.F32] if not args.no_warm_start else []):
-        wf = warm_start_form(cd, torch, g, cfg, args.steps, args.seed, fdt)
-        if wf is not None:
-            name, rec = wf
-            line["forms"][name] = {k: v for k, v in rec.items() if k != "evals"}
-            line[name + "_max_dlambda"] = float(np.abs(rec["evals"] - prim["evals"]).max())
-    if not args.no_lanczos:
-        lf = lanczos_form(cd, torch, g, cfg, args.steps, args.seed)
-        line["forms"]["f64_lanczos_upper"] = {k: v for k, v in lf.items() if k != "evals"}
-        line["f64_lanczos_upper_max_dlambda"] = float(np.abs(lf["evals"] - prim["evals"]).max())
-    if "f64" in res and not args.no_cluster:
+    if args.cluster and "f64" in res:
         line["cluster_tail"] = cluster_tail(cd, res["f64"]["evecs"], cfg.get("labels"), cfg["k"], args.seed)
-    if "f64" in res and not args.no_streaming:
-        line["streaming_warm_start"] = streaming_form(cd, torch, edges, n, cfg, res["f64"]["evecs"], args.steps,
-                                                      args.seed)
+    if args.streaming and "f64" in res:
+        line["streaming_warm_start"] = streaming_form(cd, torch, edges, n, cfg, res["f64"]["evecs"],
+                                                      max(1, min(args.steps, args.other_steps)), args.seed)
     if not args.no_cpu_baseline:
-        log("running the CPU oracle on the same workload ...")
-        cb, ref = cpu_baseline(edges, n, cfg, args.seed)
+        log("CPU oracle on the same workload ...")
+        full = n <= 500_000
+        cb, o, ref = cpu_baseline(cd, torch, g, edges, n, cfg, args.seed, full)
+        cb["c1_one_thread"] = oracle_one_thread_c1(args.seed)
+        log("oracle, sbm5k complete solve on one thread: %s" % cb["c1_one_thread"])
         line["cpu_baseline"] = cb
-        line["oracle_max_dlambda"] = float(np.abs(prim["evals"] - ref.evals).max())
-        line["oracle_iterations"] = ref.iterations
-        line["per_pair"] = per_pair_report(cd, torch, g, res, np.asarray(ref.evals))
-        log("oracle: %.2f s on %d threads, %d iterations" % (cb["value"], cb["cores"], ref.iterations))
+        if ref is not None:
+            line["oracle_iterations"] = ref.iterations
+            line["oracle_max_dlambda"] = float(np.abs(res[forms[0]]["evals"] - ref.evals).max())
+        line["per_pair"] = per_pair_report(o, res, None if ref is None else np.asarray(ref.evals))
     print(json.dumps(line), flush=True)
 
 

@@ -77,6 +77,12 @@ chebdav_status chebdav_build_laplacian(const int64_t *edges, int64_t n_edges, in
 chebdav_status chebdav_graph_info(const chebdav_graph *g, int64_t *n, int64_t *nnz,
                                   int64_t *n_isolated, int32_t *max_deg);
 
+/* The row split the sparse step uses (host output): the eight XCDs of the GPU
+ * own rows [bounds[x], bounds[x+1]), x = 0..7, contiguous ranges chosen at
+ * build time so that nnz + 4 rows is about equal across them (the local share
+ * of a 1-D row partition; Sec. 4 measures load imbalance over such shares). */
+chebdav_status chebdav_graph_row_split(const chebdav_graph *g, int64_t bounds[9]);
+
 /* Copies the CSR into caller device buffers: row_ptr int64[n+1], col int32[nnz],
  * deg int32[n], dinv double[n].  Any pointer may be NULL (skipped). */
 chebdav_status chebdav_graph_export(const chebdav_graph *g, int64_t *row_ptr, int32_t *col,

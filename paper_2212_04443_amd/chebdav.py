@@ -30,6 +30,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENOCONV", -5: "
 
 EXPORTED = [
     "chebdav_build_laplacian", "chebdav_graph_info", "chebdav_graph_export", "chebdav_graph_free",
+    "chebdav_graph_row_split",
     "chebdav_spmm", "chebdav_filter_workspace_size", "chebdav_filter",
     "chebdav_orthonormalize_workspace_size", "chebdav_orthonormalize",
     "chebdav_solve_workspace_size", "chebdav_solve", "chebdav_small_eig_workspace_size",
@@ -101,6 +102,7 @@ def _load():
         "chebdav_build_laplacian": [p, i64, i64, i32, p, P(p)],
         "chebdav_graph_info": [p, P(i64), P(i64), P(i64), P(ctypes.c_int32)],
         "chebdav_graph_export": [p, p, p, p, p, p],
+        "chebdav_graph_row_split": [p, P(i64)],
         "chebdav_spmm": [p, d, d, d, p, p, p, i64, i32, i32, p],
         "chebdav_filter_workspace_size": [p, i32, i32, P(sz)],
         "chebdav_filter": [p, p, i64, p, i64, i32, i32, d, d, d, i32, p, sz, p],
@@ -219,6 +221,13 @@ def build_laplacian(edges, n_nodes: int, device="cuda", stream=None) -> Graph:
         _check(_lib.chebdav_build_laplacian(ptr, n_edges, int(n_nodes), on_dev, _stream(stream),
                                             ctypes.byref(h)))
     return Graph(h, torch.device(device))
+
+
+def graph_row_split(g: Graph):
+    """chebdav_graph_row_split: the nine row boundaries of the per-XCD ranges."""
+    b = (ctypes.c_int64 * 9)()
+    _check(_lib.chebdav_graph_row_split(g.handle, b))
+    return [int(x) for x in b]
 
 
 def graph_export(g: Graph, stream=None):

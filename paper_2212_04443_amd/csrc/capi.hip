@@ -95,6 +95,13 @@ chebdav_status chebdav_graph_info(const chebdav_graph *gh, int64_t *n, int64_t *
     return CHEBDAV_OK;
 }
 
+chebdav_status chebdav_graph_row_split(const chebdav_graph *gh, int64_t bounds[9]) {
+    CHECK_GRAPH(gh);
+    if (!bounds) return fail(CHEBDAV_EINVAL, "bounds is NULL");
+    for (int x = 0; x < 9; ++x) bounds[x] = gh->g->xcd_row[x];
+    return CHEBDAV_OK;
+}
+
 chebdav_status chebdav_graph_export(const chebdav_graph *gh, int64_t *row_ptr, int32_t *col,
                                     int32_t *deg, double *dinv, void *hip_stream) {
     CHECK_GRAPH(gh);

@@ -32,6 +32,9 @@ from . import chebdav as cd
 DIMS = (17, 64, 64, 32)
 N_GAUSS = 16
 WEIGHTS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gcn_weights.npz")
+# optional 64-wide head for the k = 64 workloads (same inputs and hidden widths)
+DIMS_K64 = (17, 64, 64, 64)
+WEIGHTS_FILE_K64 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gcn_weights_k64.npz")
 
 
 def _sizes(dims=DIMS):

@@ -25,7 +25,7 @@ def test_committed_traffic_matches_kernel_source():
     rec = json.load(open(os.path.join(ROOT, "profiles", "k_cheb_step_sbm200k_traffic.json")))
     src = open(os.path.join(ROOT, "paper_2212_04443_amd", "csrc", "spmm.hip"), "rb").read()
     assert rec["source_sha256"] == hashlib.sha256(src).hexdigest()
-    t = bench.measured_traffic("sbm200k", 32, 200_000)
+    t = bench.measured_traffic("sbm200k", bench.step_kernel_name(200_000, 32, 8))
     assert t is not None and 1e8 < t < 1e9
 
 
@@ -37,5 +37,18 @@ def test_traffic_dropped_when_source_differs(tmp_path, monkeypatch):
     (tmp_path / "profiles" / "k_cheb_step_sbm200k_traffic.json").write_text(json.dumps(rec))
     (tmp_path / "paper_2212_04443_amd" / "csrc" / "spmm.hip").write_text("// changed\n")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.measured_traffic("sbm200k", 32, 200_000) is None
-    assert bench.measured_traffic("no_such_workload", 32, 200_000) is None
+    k = bench.step_kernel_name(200_000, 32, 8)
+    assert bench.measured_traffic("sbm200k", k) is None
+    assert bench.measured_traffic("no_such_workload", k) is None
+
+
+def test_kernel_name_follows_the_launch_rule():
+    # 16 bytes per lane, G = lanes rounded up to a power of two, deep batches
+    # once the gathered block exceeds 256 MiB
+    assert bench.step_kernel_name(200_000, 32, 8) == "k_cheb_step<double, double, 2, 16, false, false>"
+    assert bench.step_kernel_name(7_857_986, 64, 8) == "k_cheb_step<double, double, 2, 32, false, true>"
+    assert bench.step_kernel_name(7_857_986, 64, 4) == "k_cheb_step<float, float, 4, 16, false, true>"
+    assert bench.step_kernel_name(1_000_000, 64, 4) == "k_cheb_step<float, float, 4, 16, false, false>"
+    assert bench.step_kernel_name(2_000_000, 40, 8) == "k_cheb_step<double, double, 2, 32, false, true>"
+    assert bench.step_kernel_name(100, 3, 8) == "k_cheb_step<double, double, 1, 4, false, false>"
+    assert bench.step_kernel_name(100, 6, 4) == "k_cheb_step<float, float, 1, 8, false, false>"
