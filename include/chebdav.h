@@ -132,6 +132,25 @@ chebdav_status chebdav_filter(const chebdav_graph *g, const double *X, int64_t l
                               size_t ws_bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------------
+ * Filter that allocates nothing, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): chebdav_filter with its work blocks in a static device buffer of
+ * the library instead of a caller workspace.  Same arguments, kernels and
+ * results as chebdav_filter, minus the workspace.
+ * The buffer holds 64 MiB on each GPU the library runs on, until the process
+ * ends; it fits n x kb up to 3 FP64 blocks (n kb <= 2,796,000 or so, each block
+ * rounded up to 256 bytes) or 4 FP32 blocks.  Larger shapes: EUNSUPPORTED.
+ * Every call on one GPU uses the same buffer: calls that overlap on one GPU
+ * (different streams or host threads without ordering between them) race and
+ * must not be issued; calls ordered on one stream are safe.  The first call on
+ * a GPU looks up the buffer's device address (no allocation); later calls make
+ * no runtime call beyond the kernel launches.
+ * ------------------------------------------------------------------------ */
+chebdav_status chebdav_filter_noalloc(const chebdav_graph *g, const double *X, int64_t ldx, double *Y,
+                                      int64_t ldy, int kb, int m, double cut, double upper,
+                                      double scale_pt, chebdav_dtype dt, void *hip_stream);
+
+/* ------------------------------------------------------------------------
  * Block orthonormalization (Alg. 2 step 6): on return X (n x kb, device double,
  * row-major, ldx) has orthonormal columns, orthogonal to the ksub orthonormal
  * columns of V (n x ksub, device double, row-major, ldv; may be NULL if

@@ -40,7 +40,7 @@ EXPORTED = [
     "chebdav_rayleigh_ritz_workspace_size", "chebdav_rayleigh_ritz",
     "chebdav_cluster_workspace_size", "chebdav_cluster",
     "chebdav_lanczos_bounds_workspace_size", "chebdav_lanczos_bounds",
-    "chebdav_tsqr_workspace_size", "chebdav_tsqr",
+    "chebdav_tsqr_workspace_size", "chebdav_tsqr", "chebdav_filter_noalloc",
 ]
 
 
@@ -106,6 +106,7 @@ def _load():
         "chebdav_spmm": [p, d, d, d, p, p, p, i64, i32, i32, p],
         "chebdav_filter_workspace_size": [p, i32, i32, P(sz)],
         "chebdav_filter": [p, p, i64, p, i64, i32, i32, d, d, d, i32, p, sz, p],
+        "chebdav_filter_noalloc": [p, p, i64, p, i64, i32, i32, d, d, d, i32, p],
         "chebdav_orthonormalize_workspace_size": [i64, i32, i32, i32, P(sz)],
         "chebdav_orthonormalize": [p, i64, i32, p, i64, i32, i64, u64, u64, i32, P(i32), p, sz, p],
         "chebdav_tsqr_workspace_size": [i64, i32, P(sz)],
@@ -266,6 +267,18 @@ def filter(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float = 2.0, sc
         workspace = _workspace(nb.value, X.device)
     _check(_lib.chebdav_filter(g.handle, _ptr(X), _ld(X), _ptr(Y), _ld(Y), kb, m, cut, upper, scale_pt,
                                dtype, _ptr(workspace), workspace.numel(), _stream(stream)))
+    return Y
+
+
+def filter_noalloc(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float = 2.0, scale_pt: float = 0.0,
+                   dtype: int = F64, Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """chebdav_filter_noalloc: chebdav_filter on the library's static scratch
+    (no workspace; Y must be given by callers that cannot allocate)."""
+    kb = X.shape[1]
+    if Y is None:
+        Y = torch.empty_like(X)
+    _check(_lib.chebdav_filter_noalloc(g.handle, _ptr(X), _ld(X), _ptr(Y), _ld(Y), kb, m, cut, upper, scale_pt,
+                                       dtype, _stream(stream)))
     return Y
 
 

@@ -10,6 +10,12 @@ struct chebdav_graph {
     chebdav::Graph *g;
 };
 
+// Work blocks of chebdav_filter_noalloc: one copy per GPU the library runs on,
+// held until the process ends, shared by every call on that GPU.  In host code
+// this name is only a handle for hipGetSymbolAddress, never a device address.
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace chebdav {
 
 namespace {
@@ -44,6 +50,29 @@ chebdav_status fail(chebdav_status st, const char *fmt, ...) {
     va_end(ap);
     g_last_error = buf;
     return st;
+}
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the static scratch on the current GPU.
+chebdav_status static_scratch(void **out) {
+    int dev = -1;
+    CD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(CHEBDAV_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(CHEBDAV_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return CHEBDAV_OK;
 }
 
 void *pinned_host(size_t bytes, int slot) {
@@ -332,6 +361,28 @@ chebdav_status chebdav_rayleigh_ritz(const chebdav_graph *gh, const float *X, in
     CD_TRY(rayleigh_ritz(gh->g, X, ldx, k, seed, V, ldv, ritz, workspace, ws_bytes, st));
     CD_HIP(hipStreamSynchronize(st));
     return CHEBDAV_OK;
+}
+
+// Filter on the static scratch.  The device address of `scratch` is looked up
+// once per GPU (with that GPU current) on the first call made there and kept.
+chebdav_status chebdav_filter_noalloc(const chebdav_graph *gh, const double *X, int64_t ldx, double *Y,
+                                      int64_t ldy, int kb, int m, double cut, double upper, double scale_pt,
+                                      chebdav_dtype dt, void *hip_stream) {
+    CHECK_GRAPH(gh);
+    if (!X || !Y) return fail(CHEBDAV_EINVAL, "NULL block");
+    if (X == Y) return fail(CHEBDAV_EINVAL, "X and Y must not overlap");
+    if (kb < 1) return fail(CHEBDAV_EINVAL, "kb must be >= 1");
+    if (dt != CHEBDAV_F64 && dt != CHEBDAV_F32) return fail(CHEBDAV_EINVAL, "bad dtype");
+    const size_t need = filter_ws_bytes(gh->g->n, kb, dt);
+    if (need > kStaticScratchBytes)
+        return fail(CHEBDAV_EUNSUPPORTED,
+                    "chebdav_filter_noalloc: %lld x %d needs %zu bytes of work blocks, more than the %zu-byte "
+                    "static scratch (use chebdav_filter with a workspace)",
+                    (long long)gh->g->n, kb, need, kStaticScratchBytes);
+    void *ws = nullptr;
+    CD_TRY(static_scratch(&ws));
+    return run_filter(gh->g, X, ldx, Y, ldy, kb, m, cut, upper, scale_pt, dt, ws, kStaticScratchBytes,
+                      as_stream(hip_stream), nullptr, nullptr);
 }
 
 const char *chebdav_last_error(void) { return g_last_error.c_str(); }
