@@ -97,8 +97,14 @@ def build_dataset(n_graphs: int, base_seed: int = 424242, k: int = 32, kb: int =
     return data
 
 
-def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net: Net | None = None):
-    """Adam, one graph per step, graphs in a seeded random order each epoch."""
+def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net: Net | None = None,
+          fresh_features: bool = True, schedule: str = "cosine"):
+    """Adam, one graph per step, graphs in a seeded random order each epoch.
+    The input channels are random by design, so with fresh_features every epoch
+    draws new ones for every graph (seed = the epoch and graph index), instead of
+    reusing one draw per graph, which the network could fit.  The learning rate
+    follows a cosine decay to lr/20 over the epochs ("cosine") or halves every
+    third of them ("step")."""
     net = net or Net.glorot(seed)
     dims = net.dims
     m = torch.zeros_like(net.flat)
@@ -117,16 +123,23 @@ def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net
     for ep in range(epochs):
         order = rng.permutation(len(data))
         losses = []
-        lr_ep = lr * (0.5 ** (ep // max(1, epochs // 3)))
+        if schedule == "cosine":
+            lr_ep = lr * (0.05 + 0.95 * 0.5 * (1.0 + np.cos(np.pi * ep / max(1, epochs))))
+        else:
+            lr_ep = lr * (0.5 ** (ep // max(1, epochs // 3)))
         for i in order:
             d = data[i]
             g = d["g"]
             ws = ws_cache.get(g.n)
             if ws is None:
                 ws = ws_cache[g.n] = cd.gcn_workspace(g, dims)
-            out, acts = cd.gcn_forward(g, dims, d["X0"], net.W, workspace=ws)
-            loss, dX = cd.subspace_loss(out, d["U"], grad=True)
-            cd.gcn_backward(g, dims, d["X0"], net.W, acts, dX, dW=dW, workspace=ws)
+            X0 = d["X0"]
+            if fresh_features:
+                X0 = cd.gcn_features(g, seed=(seed << 32) + ep * 1_000_003 + int(i), n_gauss=N_GAUSS)
+            out, acts = cd.gcn_forward(g, dims, X0, net.W, workspace=ws)
+            loss, dX = cd.subspace_loss(out, d["U"][:, :dims[3]].contiguous() if d["U"].shape[1] != dims[3]
+                                        else d["U"], grad=True)
+            cd.gcn_backward(g, dims, X0, net.W, acts, dX, dW=dW, workspace=ws)
             step += 1
             cd.adam_step(net.flat, grad, m, v, lr_ep, step=step)
             losses.append(loss)
@@ -144,43 +157,74 @@ def warm_start(g, net: Net, seed: int = 0):
     return cd.rayleigh_ritz(g, out, seed=seed)
 
 
-def evaluate(g, net: Net, k: int, kb: int, m: int, seeds, filter_dtype=cd.F64):
-    """Random start vs warm start from the network, same solver settings, for each
-    seed (the seed drives the random vectors and the network's input channels).
-    Returns a list of dicts with iterations, filter sparse products and seconds
-    (the warm-start time includes feature generation, inference and Rayleigh-Ritz)."""
+def evaluate(g, starts: dict, k: int, kb: int, m: int, seeds, filter_dtype=cd.F64):
+    """Solves from each start with the same solver settings, for each seed (the
+    seed drives the random vectors and the networks' input channels).  starts:
+    name -> Net, or None for the random start.  Returns a list of dicts, one per
+    seed and start: iterations, sparse products, seconds (a network start's time
+    includes feature generation, inference and Rayleigh-Ritz), the eigenvalues'
+    largest difference from the random start's and the residual certificate."""
     rows = []
     for sd in seeds:
         p = cd.make_params(k_want=k, kb=kb, m=m, tol=1e-8, seed=sd, filter_dtype=filter_dtype)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        r = cd.solve(g, p)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        V0, _ = warm_start(g, net, seed=sd)
-        w = cd.solve(g, p, V_init=V0.contiguous())
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        rows.append(dict(seed=sd, random_iterations=r.stats["iterations"], warm_iterations=w.stats["iterations"],
-                         random_spmm=r.stats["n_spmm_filter"] + r.stats["n_spmm_other"],
-                         warm_spmm=w.stats["n_spmm_filter"] + w.stats["n_spmm_other"],
-                         random_s=t1 - t0, warm_s=t2 - t1,
-                         max_dlambda=float((r.evals - w.evals).abs().max().item()),
-                         warm_max_residual=w.stats["max_residual"]))
+        ref = None
+        for name, net in starts.items():
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if net is None:
+                r = cd.solve(g, p)
+            else:
+                V0, _ = warm_start(g, net, seed=sd)
+                r = cd.solve(g, p, V_init=V0.contiguous())
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if ref is None:
+                ref = r.evals
+            rows.append(dict(seed=sd, start=name, iterations=r.stats["iterations"],
+                             spmm=r.stats["n_spmm_filter"] + r.stats["n_spmm_other"], seconds=t,
+                             max_dlambda=float((r.evals - ref).abs().max().item()),
+                             max_residual=r.stats["max_residual"]))
     return rows
+
+
+def summarize(rows):
+    """Mean iterations and sparse products, median seconds, per start."""
+    out = {}
+    for name in dict.fromkeys(r["start"] for r in rows):
+        rs = [r for r in rows if r["start"] == name]
+        out[name] = dict(iterations=float(np.mean([r["iterations"] for r in rs])),
+                         spmm=float(np.mean([r["spmm"] for r in rs])),
+                         ms=1e3 * float(np.median([r["seconds"] for r in rs])),
+                         max_dlambda=max(r["max_dlambda"] for r in rs),
+                         max_residual=max(r["max_residual"] for r in rs))
+    return out
+
+
+def subspace_losses(data, net: Net):
+    """The subspace loss of the network's output against each graph's targets."""
+    out = []
+    for d in data:
+        o, _ = cd.gcn_forward(d["g"], net.dims, d["X0"], net.W)
+        out.append(cd.subspace_loss(o, d["U"][:, :net.dims[3]].contiguous())[0])
+    return out
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="train or evaluate the warm-start network on the GPU")
     ap.add_argument("cmd", choices=["train", "evaluate"])
     ap.add_argument("--workload", default="sbm1m")
-    ap.add_argument("--seeds", type=int, default=8)
+    ap.add_argument("--seeds", type=int, default=6)
     ap.add_argument("--graphs", type=int, default=512)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--seed", type=int, default=5)
-    ap.add_argument("--out", default=WEIGHTS_FILE)
+    ap.add_argument("--k", type=int, default=32, choices=[32, 64],
+                    help="output width: 32 (the default network) or 64 (the optional 64-wide head)")
+    ap.add_argument("--filter", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    dims = DIMS if a.k == 32 else DIMS_K64
+    wfile = a.out or (WEIGHTS_FILE if a.k == 32 else WEIGHTS_FILE_K64)
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -190,30 +234,29 @@ def main(argv=None):
         import synth
         edges, n, cfg = synth.make_config_graph(a.workload)
         g = cd.build_laplacian(edges, n)
-        net = Net.load()
-        rows = evaluate(g, net, cfg["k"], cfg["kb"], cfg["m"], seeds=range(1, a.seeds + 1))
+        trained = Net.load(wfile)
+        z = np.load(wfile, allow_pickle=False)
+        init_seed = int(z["seed"]) if "seed" in z.files else a.seed
+        starts = {"random": None, "untrained": Net.glorot(init_seed, trained.dims), "trained": trained}
+        rows = evaluate(g, starts, cfg["k"], cfg["kb"], cfg["m"], seeds=range(1, a.seeds + 1),
+                        filter_dtype=cd.F64 if a.filter == "f64" else cd.F32)
         for r in rows:
             log(json.dumps(r))
-        summ = dict(workload=a.workload, seeds=a.seeds,
-                    random_iterations=float(np.mean([r["random_iterations"] for r in rows])),
-                    warm_iterations=float(np.mean([r["warm_iterations"] for r in rows])),
-                    random_ms=1e3 * float(np.median([r["random_s"] for r in rows])),
-                    warm_ms=1e3 * float(np.median([r["warm_s"] for r in rows])),
-                    max_dlambda=max(r["max_dlambda"] for r in rows))
-        print(json.dumps(summ), flush=True)
+        print(json.dumps(dict(workload=a.workload, seeds=a.seeds, filter=a.filter, network=os.path.basename(wfile),
+                              starts=summarize(rows))), flush=True)
         return
 
     t0 = time.time()
-    data = build_dataset(a.graphs, log=log)
+    data = build_dataset(a.graphs, k=a.k, kb=32, log=log)
     t1 = time.time()
-    log("dataset of %d graphs (targets from the FP64 solver) in %.1f s" % (len(data), t1 - t0))
-    net, hist = train(data, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log)
+    log("dataset of %d graphs (targets from the FP64 solver, k = %d) in %.1f s" % (len(data), a.k, t1 - t0))
+    net, hist = train(data, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log, net=Net.glorot(a.seed, dims))
     torch.cuda.synchronize()
     t2 = time.time()
     log("trained %d epochs in %.1f s" % (a.epochs, t2 - t1))
-    net.save(a.out, history=np.array(hist), graphs=a.graphs, epochs=a.epochs, lr=a.lr,
+    net.save(wfile, history=np.array(hist), graphs=a.graphs, epochs=a.epochs, lr=a.lr, seed=a.seed,
              train_seconds=t2 - t1, dataset_seconds=t1 - t0)
-    log("saved %s" % a.out)
+    log("saved %s" % wfile)
 
 
 if __name__ == "__main__":
