@@ -120,7 +120,9 @@ def test_rayleigh_ritz_block(cd, oracle_mod, setup):
 def test_short_training_reduces_loss(cd, dev):
     from paper_2212_04443_amd import gcn
     data = gcn.build_dataset(4, base_seed=777)
-    net, hist = gcn.train(data, epochs=12, lr=5e-3, seed=2)
+    # one fixed draw of input channels per graph: the loss the optimizer sees is then
+    # a fixed function of the weights
+    net, hist = gcn.train(data, epochs=12, lr=5e-3, seed=2, fresh_features=False, schedule="step")
     print("training loss history", ["%.4f" % h for h in hist])
     assert hist[-1] < hist[0]
 
