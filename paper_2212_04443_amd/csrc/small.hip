@@ -7,11 +7,13 @@ namespace {
 
 constexpr int kMaxKb = 64;
 
-// Cholesky factor and inverse for Cholesky QR.  One workgroup of 256 threads on
-// a 16 x 16 grid; thread (ti, tj) owns the entries (ti + 16 a, tj + 16 b) of the
+// Cholesky factor and inverse for Cholesky QR.  One wavefront of 64 threads on
+// an 8 x 8 grid; thread (ti, tj) owns the entries (ti + 8 a, tj + 8 b) of the
 // kb x kb working matrix in LDS, so every step updates all entries in parallel
-// without index arithmetic.  Two barriers per step: the diagonal of R is kept
-// apart (dR), so a step's scaling never overwrites what other threads read.
+// without index arithmetic.  The 2 kb steps are sequential, so a single
+// wavefront (whose barriers cost nothing) beats more threads that have to meet
+// at two barriers per step.  The diagonal of R is kept apart (dR), so a step's
+// scaling never overwrites what other threads read.
 //   scaled = 1: x_j = sqrt(G_jj) is column j's norm after projection; it is
 //     dependent if x_j < 1e-10 * norm0_j (or not finite/positive).  The
 //     remaining columns are scaled to unit norm (Gt = S G S, S = diag(1/x)) and
@@ -23,11 +25,13 @@ constexpr int kMaxKb = 64;
 // the smallest diagonal entry of the (scaled) factor is below 0.01, i.e. R^{-1}
 // may amplify the block's residual components along the basis by more than 100.
 // R^{-1} comes from Gauss-Jordan elimination on [R | I] from the last row up.
-__global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G, int kb,
+constexpr int kCholP = 8;  // thread grid edge: kCholP^2 threads
+
+__global__ void __launch_bounds__(kCholP * kCholP) k_chol_rinv(const double *__restrict__ G, int kb,
                                                    const double *__restrict__ norm0,
                                                    double *__restrict__ Rinv, int *__restrict__ dep,
                                                    int scaled) {
-    constexpr int P = 16, TT = kMaxKb / P;
+    constexpr int P = kCholP, TT = kMaxKb / P, NT = P * P;
     // R in the upper triangle of A; B = R^{-1} (upper) kept transposed in the
     // strict lower triangle of A, its diagonal in bd
     __shared__ double A[kMaxKb][kMaxKb + 1];
@@ -118,7 +122,7 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
     // ||R^{-1}||_F^2 of the column-scaled factor (its columns have unit norm,
     // so kappa(R) <= sqrt(kb) ||R^{-1}||_F): per-thread sums over a fixed set of
     // entries, then a fixed-order tree (deterministic)
-    __shared__ double fro[256];
+    __shared__ double fro[NT];
     {
         double acc = 0.0;
 #pragma unroll
@@ -134,7 +138,7 @@ __global__ void __launch_bounds__(256) k_chol_rinv(const double *__restrict__ G,
         fro[tid] = acc;
     }
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
+    for (int h = NT / 2; h > 0; h >>= 1) {
         if (tid < h) fro[tid] += fro[tid + h];
         __syncthreads();
     }
@@ -229,7 +233,7 @@ __global__ void __launch_bounds__(256) k_small_gemm(const double *__restrict__ A
 chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *Rinv, int *dep,
                          int scaled, hipStream_t st) {
     if (kb < 1 || kb > kMaxKb) return fail(CHEBDAV_EUNSUPPORTED, "block size %d outside [1, %d]", kb, kMaxKb);
-    hipLaunchKernelGGL(k_chol_rinv, dim3(1), dim3(256), 0, st, G, kb, norm0, Rinv, dep, scaled);
+    hipLaunchKernelGGL(k_chol_rinv, dim3(1), dim3(kCholP * kCholP), 0, st, G, kb, norm0, Rinv, dep, scaled);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }
