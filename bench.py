@@ -81,6 +81,7 @@ FORMS = {
     "f64_tsqr": ("f64", "tsqr", "random"),
     "gcn_f64": ("f64", "cholqr", "gcn"),
     "gcn_f32": ("f32", "cholqr", "gcn"),
+    "gcn64_f32": ("f32", "cholqr", "gcn64"),
     "f64_lanczos": ("f64", "cholqr", "lanczos"),
 }
 
@@ -88,8 +89,9 @@ FORMS = {
 def run_form(cd, torch, g, cfg, form, steps, warmup, seed, net=None):
     """Times `steps` complete solves after `warmup` untimed ones.  GCN forms
     include feature generation, inference and Rayleigh-Ritz of the network
-    output in every timed solve; the Lanczos form includes its 10-step bound
-    estimate."""
+    output in every timed solve (gcn: the 32-wide network, its block padded with
+    random columns at k = 64; gcn64: the 64-wide head); the Lanczos form
+    includes its 10-step bound estimate."""
     fdt, orth, start = FORMS[form]
     dt = cd.F32 if fdt == "f32" else cd.F64
 
@@ -102,9 +104,9 @@ def run_form(cd, torch, g, cfg, form, steps, warmup, seed, net=None):
     extra = {}
 
     def once():
-        if start == "gcn":
+        if start in ("gcn", "gcn64"):
             from paper_2212_04443_amd import gcn
-            V0, _ = gcn.warm_start(g, net, seed=seed)
+            V0, _ = gcn.warm_start(g, net[start], seed=seed)
             return cd.solve(g, p0, V_init=V0.contiguous(), workspace=ws)
         if start == "lanczos":
             _, hi, _, _ = cd.lanczos_bounds(g, 10, seed=seed)
@@ -401,10 +403,12 @@ def main():
     for f in forms:
         if f not in FORMS:
             ap.error("unknown form %s" % f)
-    net = None
-    if any(FORMS[f][2] == "gcn" for f in forms):
+    net = {}
+    if any(FORMS[f][2] in ("gcn", "gcn64") for f in forms):
         from paper_2212_04443_amd import gcn
-        net = gcn.Net.load()
+        net["gcn"] = gcn.Net.load()
+        if any(FORMS[f][2] == "gcn64" for f in forms):
+            net["gcn64"] = gcn.Net.load(gcn.WEIGHTS_FILE_K64)
     res = {}
     for i, f in enumerate(forms):
         steps = args.steps if i == 0 else max(1, min(args.steps, args.other_steps))

@@ -12,9 +12,11 @@ Training runs on the GPU through the library's own kernels
 chebdav_adam_step): the targets are the k = 32 eigenvectors the FP64 solver
 computes for seeded SBM graphs with N in [10k, 50k], 8..32 blocks, intra-block
 degree 10..30 and inter-block degree 2..6; the loss is the rotation-invariant
-subspace loss.
+subspace loss.  An optional 64-wide head (17 -> 64 -> 64 -> 64, k = 64
+targets; gcn_weights_k64.npz) serves the k = 64 workloads.
 
-    python -m paper_2212_04443_amd.gcn train --graphs 512 --epochs 20 --out <file.npz>
+    python -m paper_2212_04443_amd.gcn train --graphs 512 --epochs 20 --lr 5e-3 --fixed-features --schedule step
+    python -m paper_2212_04443_amd.gcn evaluate --workload sbm1m --seeds 6     (random / untrained / trained)
 """
 
 from __future__ import annotations
@@ -98,7 +100,7 @@ def build_dataset(n_graphs: int, base_seed: int = 424242, k: int = 32, kb: int =
 
 
 def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net: Net | None = None,
-          fresh_features: bool = True, schedule: str = "cosine"):
+          fresh_features: bool = True, schedule: str = "cosine", targets: str = "all"):
     """Adam, one graph per step, graphs in a seeded random order each epoch.
     The input channels are random by design, so with fresh_features every epoch
     draws new ones for every graph (seed = the epoch and graph index), instead of
@@ -137,8 +139,11 @@ def train(data, epochs: int = 20, lr: float = 3e-3, seed: int = 5, log=None, net
             if fresh_features:
                 X0 = cd.gcn_features(g, seed=(seed << 32) + ep * 1_000_003 + int(i), n_gauss=N_GAUSS)
             out, acts = cd.gcn_forward(g, dims, X0, net.W, workspace=ws)
-            loss, dX = cd.subspace_loss(out, d["U"][:, :dims[3]].contiguous() if d["U"].shape[1] != dims[3]
-                                        else d["U"], grad=True)
+            kt = min(dims[3], d["U"].shape[1])
+            if targets == "cluster":  # the eigenvectors of the planted clusters only
+                kt = min(kt, int(d["meta"]["blocks"]))
+            U = d["U"] if kt == d["U"].shape[1] else d["U"][:, :kt].contiguous()
+            loss, dX = cd.subspace_loss(out, U, grad=True)
             cd.gcn_backward(g, dims, X0, net.W, acts, dX, dW=dW, workspace=ws)
             step += 1
             cd.adam_step(net.flat, grad, m, v, lr_ep, step=step)
@@ -221,6 +226,11 @@ def main(argv=None):
     ap.add_argument("--k", type=int, default=32, choices=[32, 64],
                     help="output width: 32 (the default network) or 64 (the optional 64-wide head)")
     ap.add_argument("--filter", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--fixed-features", action="store_true",
+                    help="one draw of input channels per graph for the whole training (default: fresh every epoch)")
+    ap.add_argument("--schedule", default="cosine", choices=["cosine", "step"])
+    ap.add_argument("--targets", default="all", choices=["all", "cluster"],
+                    help="all k eigenvectors, or only those of the planted clusters (min(blocks, k))")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     dims = DIMS if a.k == 32 else DIMS_K64
@@ -250,11 +260,13 @@ def main(argv=None):
     data = build_dataset(a.graphs, k=a.k, kb=32, log=log)
     t1 = time.time()
     log("dataset of %d graphs (targets from the FP64 solver, k = %d) in %.1f s" % (len(data), a.k, t1 - t0))
-    net, hist = train(data, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log, net=Net.glorot(a.seed, dims))
+    net, hist = train(data, epochs=a.epochs, lr=a.lr, seed=a.seed, log=log, net=Net.glorot(a.seed, dims),
+                      fresh_features=not a.fixed_features, schedule=a.schedule, targets=a.targets)
     torch.cuda.synchronize()
     t2 = time.time()
     log("trained %d epochs in %.1f s" % (a.epochs, t2 - t1))
     net.save(wfile, history=np.array(hist), graphs=a.graphs, epochs=a.epochs, lr=a.lr, seed=a.seed,
+             fresh_features=not a.fixed_features, schedule=a.schedule, targets=a.targets,
              train_seconds=t2 - t1, dataset_seconds=t1 - t0)
     log("saved %s" % wfile)
 

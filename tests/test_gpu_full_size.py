@@ -135,3 +135,47 @@ def test_chunglu8m_full_size(cd, oracle_mod, dev):
     print("chunglu8m: FP64 random %d iterations (max residual %.2e), FP32 + warm start %d (%.2e); "
           "max |dlambda| %.2e; lambda_64 = %.6f" % (it0, m0, it1, m1, dl, ev0[-1]))
     assert dl <= 1e-8
+
+
+def test_warm_start_ablation_sbm1m(cd, oracle_mod, dev):
+    """What the learned warm start contributes, on the held-out 1M-node SBM
+    (32 blocks): solves from a random start, from the untrained network (the
+    trained one's Glorot initialization, same architecture and inputs) and from
+    the trained network, three seeds each, all to the same eigenpairs.  The
+    trained start must take fewer iterations than the random one on average, and
+    the trained network's subspace loss on held-out training-distribution graphs
+    (targets: the oracle's eigenvectors) must be below the untrained network's.
+    The untrained network's iterations are reported beside them: the three
+    propagations through A-hat of random input already do most of the work."""
+    import os
+    from paper_2212_04443_amd import gcn
+    if not os.path.exists(gcn.WEIGHTS_FILE):
+        pytest.skip("no trained weights committed")
+    trained = gcn.Net.load()
+    z = np.load(gcn.WEIGHTS_FILE, allow_pickle=False)
+    untrained = gcn.Net.glorot(int(z["seed"]) if "seed" in z.files else 5, trained.dims)
+    e, n, cfg = synth.make_config_graph("sbm1m")
+    g = cd.build_laplacian(e, n)
+    print("case warm-start ablation sbm1m", flush=True)
+    rows = gcn.evaluate(g, {"random": None, "untrained": untrained, "trained": trained}, 32, 32, 15,
+                        seeds=[1, 2, 3])
+    summ = gcn.summarize(rows)
+    print("sbm1m iterations: random %.2f, untrained %.2f, trained %.2f" %
+          (summ["random"]["iterations"], summ["untrained"]["iterations"], summ["trained"]["iterations"]))
+    assert all(r["max_dlambda"] <= 1e-10 and r["max_residual"] <= 1e-8 for r in rows)
+    assert summ["trained"]["iterations"] < summ["random"]["iterations"]
+    del g
+    import torch
+    lt, lu = [], []
+    for i in range(3):
+        e2, n2, meta = gcn.training_graph(20_000 + i, base_seed=777)
+        o = oracle_mod.build_csr(e2, n2)
+        U = oracle_mod.bchdav(o, oracle_mod.Params(k_want=32, kb=32, m=15, seed=1)).evecs
+        g2 = cd.build_laplacian(e2, n2)
+        X0 = cd.gcn_features(g2, seed=31 + i, n_gauss=gcn.N_GAUSS)
+        Ut = torch.from_numpy(np.ascontiguousarray(U)).cuda()
+        for net, acc in ((trained, lt), (untrained, lu)):
+            out, _ = cd.gcn_forward(g2, net.dims, X0, net.W)
+            acc.append(cd.subspace_loss(out, Ut)[0])
+    print("held-out subspace loss: untrained %.4f, trained %.4f" % (np.mean(lu), np.mean(lt)))
+    assert np.mean(lt) < np.mean(lu)

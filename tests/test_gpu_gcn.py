@@ -75,6 +75,20 @@ def test_loss_and_gradient_match_oracle(cd, oracle_mod, setup):
     assert _rel(dX.cpu().numpy(), wdX) <= 1e-6
 
 
+def test_loss_with_fewer_targets_matches_oracle(cd, oracle_mod, setup):
+    """Training against the planted-cluster eigenvectors only (6 blocks here):
+    32 output columns, 6 target columns."""
+    import torch
+    s = setup
+    out, _ = cd.gcn_forward(s["g"], s["dims"], s["X0t"], s["Wt"])
+    lam, Q = np.linalg.eigh(oracle_mod.dense_laplacian(s["o"]))
+    U = np.ascontiguousarray(Q[:, :6])
+    loss, dX = cd.subspace_loss(out, torch.from_numpy(U).cuda())
+    wl, wdX = s["ogcn"].subspace_loss(out.cpu().numpy().astype(np.float64), U)
+    assert abs(loss - wl) <= 1e-10
+    assert _rel(dX.cpu().numpy(), wdX) <= 1e-6
+
+
 def test_features(cd, setup):
     s = setup
     X1 = cd.gcn_features(s["g"], seed=5).cpu().numpy()

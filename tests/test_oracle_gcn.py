@@ -46,6 +46,27 @@ def test_loss_gradient_finite_differences(small):
         assert abs(fd - dX[i, j]) <= 1e-7 * max(1.0, abs(fd))
 
 
+def test_loss_gradient_fewer_targets_than_columns(small):
+    """Targets narrower than the output block (the planted-cluster eigenvectors
+    only): the loss and its gradient keep their definitions with k = ku."""
+    gcn, csr, dims, W, X0, U = small
+    X = np.random.default_rng(8).standard_normal((160, 4))
+    U2 = U[:, :2]
+    L, dX = gcn.subspace_loss(X, U2)
+    assert 0.0 <= L <= 1.0
+    h = 1e-6
+    rng = np.random.default_rng(9)
+    for _ in range(12):
+        i, j = rng.integers(0, 160), rng.integers(0, 4)
+        Xp = X.copy(); Xp[i, j] += h
+        Xm = X.copy(); Xm[i, j] -= h
+        fd = (gcn.subspace_loss(Xp, U2)[0] - gcn.subspace_loss(Xm, U2)[0]) / (2 * h)
+        assert abs(fd - dX[i, j]) <= 1e-7 * max(1.0, abs(fd))
+    # a block that contains the targets has loss 0 whatever its other columns
+    Xc = np.concatenate([U2 @ np.array([[1.0, 2.0], [0.5, -1.0]]), X[:, :2]], 1)
+    assert abs(gcn.subspace_loss(Xc, U2)[0]) < 1e-12
+
+
 def test_weight_gradients_finite_differences(small):
     gcn, csr, dims, W, X0, U = small
     out, acts = gcn.forward(csr, X0, W)
