@@ -7,13 +7,13 @@ namespace {
 
 constexpr int kMaxKb = 64;
 
-// Cholesky factor and inverse for Cholesky QR.  One wavefront of 64 threads on
-// an 8 x 8 grid; thread (ti, tj) owns the entries (ti + 8 a, tj + 8 b) of the
+// Cholesky factor and inverse for Cholesky QR.  One workgroup of 256 threads on
+// a 16 x 16 grid; thread (ti, tj) owns the entries (ti + 16 a, tj + 16 b) of the
 // kb x kb working matrix in LDS, so every step updates all entries in parallel
-// without index arithmetic.  The 2 kb steps are sequential, so a single
-// wavefront (whose barriers cost nothing) beats more threads that have to meet
-// at two barriers per step.  The diagonal of R is kept apart (dR), so a step's
-// scaling never overwrites what other threads read.
+// without index arithmetic.  Two barriers per step: the diagonal of R is kept
+// apart (dR), so a step's scaling never overwrites what other threads read.
+// (One wavefront on an 8 x 8 grid, with no barrier waits, measured twice as
+// slow: each step's sixteen LDS updates per thread then run back to back.)
 //   scaled = 1: x_j = sqrt(G_jj) is column j's norm after projection; it is
 //     dependent if x_j < 1e-10 * norm0_j (or not finite/positive).  The
 //     remaining columns are scaled to unit norm (Gt = S G S, S = diag(1/x)) and
@@ -25,7 +25,7 @@ constexpr int kMaxKb = 64;
 // the smallest diagonal entry of the (scaled) factor is below 0.01, i.e. R^{-1}
 // may amplify the block's residual components along the basis by more than 100.
 // R^{-1} comes from Gauss-Jordan elimination on [R | I] from the last row up.
-constexpr int kCholP = 8;  // thread grid edge: kCholP^2 threads
+constexpr int kCholP = 16;  // thread grid edge: kCholP^2 threads
 
 __global__ void __launch_bounds__(kCholP * kCholP) k_chol_rinv(const double *__restrict__ G, int kb,
                                                    const double *__restrict__ norm0,
