@@ -229,7 +229,9 @@ typedef struct {
     chebdav_dtype filter_dtype;  /* F64, or F32 for the mixed-precision form              */
     double f32_switch_tol;  /* F32 form: the filter runs in FP64 once the smallest residual
                                among the non-converged leading pairs falls below this
-                               (0 -> 1e-5); every other step is always FP64               */
+                               (0 -> 3e-7, about five FP32 unit roundoffs), or after two
+                               FP32 iterations in a row that neither locked a pair nor
+                               halved that residual; every other step is always FP64      */
     uint64_t seed;          /* Philox key for all random vectors                           */
     int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
     chebdav_orth orth;      /* orthonormalization of new blocks (default CHOLQR)           */

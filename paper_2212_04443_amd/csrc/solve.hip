@@ -73,7 +73,7 @@ chebdav_status resolve(const chebdav_params *p, int64_t n, Resolved &r) {
     r.low_nwb0 = (std::isnan(p->low_nwb0) || p->low_nwb0 <= r.lowb)
                      ? r.lowb + (r.upperb - r.lowb) * r.k_want / (double)n
                      : p->low_nwb0;
-    r.f32_switch_tol = p->f32_switch_tol > 0 ? p->f32_switch_tol : 1e-5;
+    r.f32_switch_tol = p->f32_switch_tol > 0 ? p->f32_switch_tol : 3e-7;
     r.fdt = p->filter_dtype;
     r.orth = p->orth;
     r.seed = p->seed;
@@ -303,6 +303,8 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
     };
     int it = 0, cert_rounds = 0;
     bool cert_failed = false;
+    double f32_best = INFINITY;  // smallest open residual seen while filtering in FP32
+    int f32_stall = 0;           // FP32 iterations in a row without progress
     std::vector<double> D(am), res(kb);
     while (it < r.itmax) {
         ++it;
@@ -532,8 +534,18 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             const double med = median_of(std::vector<double>(Dact.begin(), Dact.begin() + kact));
             if (lowb < med && med < upperb) low_nwb = med;
         }
-        // mixed precision: FP64 filtering once the leading open residual is small
-        if (!use_f64_filter && min_open_res < r.f32_switch_tol) use_f64_filter = true;
+        // mixed precision: FP64 filtering once the leading open residual is small,
+        // or once FP32 filtering stops making progress (two iterations in a row
+        // that neither locked a pair nor halved the smallest open residual)
+        if (!use_f64_filter) {
+            if (ec > 0 || min_open_res < 0.5 * f32_best) {
+                f32_stall = 0;
+            } else {
+                ++f32_stall;
+            }
+            f32_best = std::min(f32_best, min_open_res);
+            if (min_open_res < r.f32_switch_tol || f32_stall >= 2) use_f64_filter = true;
+        }
         if (r.log_cb) r.log_cb(&rec, r.log_user);
     }
     S.iterations = it;

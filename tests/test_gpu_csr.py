@@ -99,3 +99,27 @@ def test_dinv_exhaustive(cd, dev):
     want = np.zeros_like(dd)
     want[1:] = 1.0 / np.sqrt(dd[1:])
     assert np.array_equal(got.view(np.uint64), want.view(np.uint64))
+
+
+@pytest.mark.parametrize("case", ["chung_lu", "sbm", "tiny"])
+def test_row_split_covers_rows_and_balances(cd, oracle_mod, dev, case):
+    """chebdav_graph_row_split: nine non-decreasing boundaries from 0 to n (the
+    eight per-XCD row ranges of the sparse step); on a large graph every range
+    carries about one eighth of nnz + 4 rows (largest range within 10 % of the
+    mean, or within one row's weight of it)."""
+    if case == "chung_lu":
+        e, n = synth.chung_lu(200_000, seed=5)
+    elif case == "sbm":
+        e, _ = synth.sbm(100_000, 16, d_in=20, d_out=4, uneven=True, seed=6)
+        n = 100_000
+    else:
+        e, n = synth.path_graph(5), 5
+    g = cd.build_laplacian(e, n)
+    b = np.array(cd.graph_row_split(g))
+    assert b[0] == 0 and b[-1] == n and (np.diff(b) >= 0).all()
+    if case != "tiny":
+        o = oracle_mod.build_csr(e, n)
+        w = np.diff(o.row_ptr) + 4
+        cw = np.concatenate([[0], np.cumsum(w)])
+        per = cw[b[1:]] - cw[b[:-1]]
+        assert per.max() <= max(1.1 * cw[-1] / 8, cw[-1] / 8 + w.max())

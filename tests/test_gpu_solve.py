@@ -348,3 +348,32 @@ def test_chung_lu_500k_oracle_parity(cd, oracle_mod, dev):
     ang = sin_max_angle(ref.evecs, V)
     print("chung-lu 500k: largest principal angle %.3g" % ang)
     assert ang <= 1e-4
+
+
+def test_f32_form_stall_guard(cd, oracle_mod, dev):
+    """FP32 form asked for a residual an FP32-filtered block cannot deliver
+    (tol 1e-9; FP32 filtering levels off near 4e-8 here) with a switch level it
+    cannot reach either (1e-14): the filter must hand over to FP64 once FP32
+    iterations stop making progress (none locks a pair or halves the smallest
+    open residual, twice in a row), and the solve then converges to the oracle's
+    eigenpairs at that tolerance."""
+    n = 20_000
+    e, _ = synth.sbm(n, 16, d_in=20, d_out=4, uneven=True, seed=3)
+    o = oracle_mod.build_csr(e, n)
+    o_csr_cache[0] = o
+    ref = oracle_mod.bchdav(o, oracle_mod.Params(k_want=16, kb=8, m=15, seed=7, tol=1e-9))
+    assert ref.status == "ok"
+    log = []
+    _, ev, V, st = _gpu_solve(cd, e, n, k_want=16, kb=8, m=15, seed=7, tol=1e-9, filter_dtype=cd.F32,
+                              f32_switch_tol=1e-14, log=log)
+    res = _fresh_residuals(oracle_mod, ev, V)
+    flags = [r["filter_f32"] for r in log]
+    print("stall guard: %d iterations (oracle %d), FP32 steps %d of %d, filter per iteration %s, max res %.3g"
+          % (st["iterations"], ref.iterations, st["n_spmm_filter_f32"], st["n_spmm_filter"],
+             "".join("4" if f else "8" for f in flags), res.max()))
+    assert st["converged"] == 16 and res.max() <= 1e-9 * 1.01
+    assert np.abs(ev - ref.evals).max() <= 1e-10
+    assert sin_max_angle(ref.evecs, V) <= 1e-6
+    assert 0 < st["n_spmm_filter_f32"] < st["n_spmm_filter"]
+    k = flags.index(0)
+    assert all(flags[:k]) and not any(flags[k:])
