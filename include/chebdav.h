@@ -231,7 +231,8 @@ typedef struct {
                                among the non-converged leading pairs falls below this
                                (0 -> 3e-7, about five FP32 unit roundoffs), or after two
                                FP32 iterations in a row that neither locked a pair nor
-                               halved that residual; every other step is always FP64      */
+                               halved that residual nor halved the largest open residual
+                               among the wanted pairs; every other step is always FP64    */
     uint64_t seed;          /* Philox key for all random vectors                           */
     int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
     chebdav_orth orth;      /* orthonormalization of new blocks (default CHOLQR)           */

@@ -304,6 +304,7 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
     int it = 0, cert_rounds = 0;
     bool cert_failed = false;
     double f32_best = INFINITY;  // smallest open residual seen while filtering in FP32
+    double f32_best_max = INFINITY;  // smallest value of the largest wanted open residual in FP32
     int f32_stall = 0;           // FP32 iterations in a row without progress
     std::vector<double> D(am), res(kb);
     while (it < r.itmax) {
@@ -404,8 +405,11 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         double min_open_res = INFINITY;
         rec.min_residual = INFINITY;
         rec.max_residual = 0.0;
+        double max_open_res = 0.0;  // largest open residual among the wanted pairs
+        const int n_wanted = std::min(nres, r.k_want - kc);
         for (int i = 0; i < nres; ++i) {
             if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
+            if (!(res[i] <= r.tol) && i < n_wanted) max_open_res = std::max(max_open_res, res[i]);
             rec.min_residual = std::min(rec.min_residual, res[i]);
             rec.max_residual = std::max(rec.max_residual, res[i]);
         }
@@ -535,15 +539,19 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             if (lowb < med && med < upperb) low_nwb = med;
         }
         // mixed precision: FP64 filtering once the leading open residual is small,
-        // or once FP32 filtering stops making progress (two iterations in a row
-        // that neither locked a pair nor halved the smallest open residual)
+        // or once FP32 filtering stops making progress on the whole wanted block
+        // (two iterations in a row that neither locked a pair nor halved the
+        // smallest open residual nor the largest open residual among the wanted
+        // pairs: a leading pair held at its FP32 floor does not stop the FP32
+        // filter while the rest of the block still converges at half the bytes)
         if (!use_f64_filter) {
-            if (ec > 0 || min_open_res < 0.5 * f32_best) {
+            if (ec > 0 || min_open_res < 0.5 * f32_best || max_open_res < 0.5 * f32_best_max) {
                 f32_stall = 0;
             } else {
                 ++f32_stall;
             }
             f32_best = std::min(f32_best, min_open_res);
+            f32_best_max = std::min(f32_best_max, max_open_res);
             if (min_open_res < r.f32_switch_tol || f32_stall >= 2) use_f64_filter = true;
         }
         if (r.log_cb) r.log_cb(&rec, r.log_user);

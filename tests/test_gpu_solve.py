@@ -59,6 +59,20 @@ def test_sbm20k_k16_parity(cd, oracle_mod, dev):
     assert sin_max_angle(ref.evecs, V) <= 1e-6
 
 
+@pytest.mark.parametrize("k,kb,m", [(12, 7, 9), (11, 5, 11), (12, 12, 7), (5, 1, 15), (13, 3, 13)])
+def test_block_sizes_parity(cd, oracle_mod, dev, k, kb, m):
+    """Block sizes off the powers of two (kb = 3, 5, 7: padded sparse-step columns and
+    partial MFMA tiles), single-vector blocks (kb = 1), k not a multiple of kb and kb = k,
+    on a 6000-node SBM whose 12 planted blocks put a gap of 0.43 after the 12th
+    eigenvalue (inner restarts fire in four of the five cases).  The subspace angle is
+    checked for k = 12, the only case with a gap above 0.01 after the k-th eigenvalue."""
+    e, _ = synth.sbm(6000, 12, d_in=18, d_out=3, uneven=True, seed=11)
+    print("case block sizes k=%d kb=%d m=%d" % (k, kb, m), flush=True)
+    ev, V, st, ref = _parity(cd, oracle_mod, e, 6000, k, kb, m, seed=3, it_slack=3 if kb == 1 else 2)
+    if k == 12:
+        assert sin_max_angle(ref.evecs, V) <= 1e-6
+
+
 def test_dense_eigh_small(cd, oracle_mod, dev):
     n = 1500
     e, _ = synth.sbm(n, 6, d_in=12, d_out=2, uneven=True, seed=4)
@@ -355,7 +369,7 @@ def test_f32_form_stall_guard(cd, oracle_mod, dev):
     (tol 1e-9; FP32 filtering levels off near 4e-8 here) with a switch level it
     cannot reach either (1e-14): the filter must hand over to FP64 once FP32
     iterations stop making progress (none locks a pair or halves the smallest
-    open residual, twice in a row), and the solve then converges to the oracle's
+    open residual or the largest wanted open residual, twice in a row), and the solve then converges to the oracle's
     eigenpairs at that tolerance."""
     n = 20_000
     e, _ = synth.sbm(n, 16, d_in=20, d_out=4, uneven=True, seed=3)
