@@ -157,11 +157,12 @@ chebdav_status chebdav_filter_noalloc(const chebdav_graph *g, const double *X, i
  * ksub == 0), and spans the same space as (I - V V^T) X_in when that has full
  * numerical rank.  Method: two block classical Gram-Schmidt passes against V,
  * then (method CHOLQR) Cholesky QR with a dependence test; when the smallest
- * diagonal entry of the scaled Cholesky factor R is below 0.01, or the bound
- * sqrt(kb) ||R^{-1}||_F on its condition number exceeds 100, a third pass
- * against V and a second Cholesky QR, otherwise one Newton-Schulz step
- * X <- X (3 I - X^T X) / 2 (X^T X is then within O(1e4 eps) of I, and the step
- * squares that deviation); or (method TSQR) the same with Householder TSQR
+ * diagonal entry of the scaled Cholesky factor R is below 0.01, or
+ * ||R^{-1}||_F (a bound on the amplification ||R^{-1}||_2 of components along V)
+ * exceeds 100, a third pass against V and a second Cholesky QR, otherwise one
+ * Newton-Schulz step X <- X (3 I - X^T X) / 2 (R has unit columns, so
+ * kappa(R) <= 8 ||R^{-1}||_2 <= 800, X^T X is within O(kappa^2 eps) of I, and
+ * the step squares that deviation); or (method TSQR) the same with Householder TSQR
  * (chebdav_tsqr) in place of each Cholesky QR, its R deciding dependence with
  * the same thresholds, and no second pass unless the third projection ran.  A column whose norm after projection
  * is below 1e-10 of its norm before, or whose squared pivot in the

@@ -14,8 +14,8 @@
 //             columns before it).  Dependent columns are replaced by Philox
 //             columns and everything is redone.
 //   BCGS      one more pass against V when the smallest scaled pivot is below
-//             0.01 or the bound sqrt(kb) ||R^{-1}||_F on the condition number
-//             of the scaled factor exceeds 100 (R^{-1} may then amplify the
+//             0.01 or ||R^{-1}||_F of the scaled factor (a bound on its
+//             ||R^{-1}||_2) exceeds 100 (R^{-1} may then amplify the
 //             remaining non-orthogonality to V above rounding level), then a
 //             second, plain CholQR; otherwise one Newton-Schulz step
 //             X <- X (3 I - X^T X) / 2 in its place.
@@ -157,10 +157,10 @@ chebdav_status orthonormalize(const Seg2 &V, double *X, int64_t ldx, int kb, int
     CD_TRY(update(xs, s.Rinv, kb, 1.0, 0.0, X, ldx, kb, n, st));
     // a third projection only when R^{-1} can have amplified the remaining
     // components along V above rounding level (smallest scaled pivot < 0.01, or
-    // the condition bound sqrt(kb) ||R^{-1}||_F of the scaled factor above
-    // 100); then a second Cholesky QR.  Otherwise the first Cholesky QR left
-    // X^T X within O(kappa^2 eps) of I with kappa <= 100, and one Newton-Schulz
-    // step X (3 I - X^T X) / 2 squares that deviation.
+    // ||R^{-1}||_F of the scaled factor above 100); then a second Cholesky QR.
+    // Otherwise the first Cholesky QR left X^T X within O(kappa^2 eps) of I with
+    // kappa <= 8 ||R^{-1}||_2 <= 800 (unit columns, kb <= 64), and one
+    // Newton-Schulz step X (3 I - X^T X) / 2 squares that deviation.
     if (hdep[kb + 1]) {
         CD_TRY(project_out(V, X, ldx, kb, n, s, st));
         CD_TRY(gram(xs, X, ldx, kb, n, s.G, kb, s.part, st));

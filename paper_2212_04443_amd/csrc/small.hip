@@ -22,8 +22,9 @@ constexpr int kMaxKb = 64;
 //     orthonormal columns.
 //   scaled = 0: plain G = R^T R, Rinv = R^{-1}; a non-positive pivot sets dep[kb].
 // dep[j] (j < kb) = 1 for dependent columns, dep[kb] = 1 if any, dep[kb+1] = 1 if
-// the smallest diagonal entry of the (scaled) factor is below 0.01, i.e. R^{-1}
-// may amplify the block's residual components along the basis by more than 100.
+// ||R^{-1}||_2 <= 100 is not certain for the (scaled) factor (its smallest
+// diagonal entry is below 0.01, or ||R^{-1}||_F exceeds 100): R^{-1} may then
+// amplify the block's residual components along the basis by more than 100.
 // R^{-1} comes from Gauss-Jordan elimination on [R | I] from the last row up.
 constexpr int kCholP = 16;  // thread grid edge: kCholP^2 threads
 
@@ -119,9 +120,9 @@ __global__ void __launch_bounds__(kCholP * kCholP) k_chol_rinv(const double *__r
             const int i = ti + P * a, j = tj + P * b;
             if (i < kb && j < kb) Rinv[i * kb + j] = s[i] * (i < j ? A[j][i] : i == j ? bd[i] : 0.0);
         }
-    // ||R^{-1}||_F^2 of the column-scaled factor (its columns have unit norm,
-    // so kappa(R) <= sqrt(kb) ||R^{-1}||_F): per-thread sums over a fixed set of
-    // entries, then a fixed-order tree (deterministic)
+    // ||R^{-1}||_F^2 of the column-scaled factor, an upper bound of ||R^{-1}||_2^2:
+    // per-thread sums over a fixed set of entries, then a fixed-order tree
+    // (deterministic)
     __shared__ double fro[NT];
     {
         double acc = 0.0;
@@ -150,11 +151,11 @@ __global__ void __launch_bounds__(kCholP * kCholP) k_chol_rinv(const double *__r
             if (!d[j]) rmin = fmin(rmin, dR[j]);
         }
         dep[kb] = any;
-        // a second full pass unless kappa(R) <= 100 is certain: then the first
-        // pass left X^T X within about kappa^2 eps of I and V^T X within about
-        // kappa eps, and one Newton-Schulz step suffices
-        const double kappa2 = (double)kb * fro[0];
-        dep[kb + 1] = rmin < 0.01 || !(kappa2 <= 1e4);
+        // a second full pass unless ||R^{-1}||_2 <= 100 is certain: then V^T X
+        // grew by at most 100 in the first pass, and since the scaled factor has
+        // unit columns (||R||_2 <= sqrt(kb) <= 8) kappa(R) <= 800, so X^T X is
+        // within about kappa^2 eps of I and one Newton-Schulz step suffices
+        dep[kb + 1] = rmin < 0.01 || !(fro[0] <= 1e4);
     }
     if (tid < kb) dep[tid] = d[tid];
 }

@@ -230,9 +230,9 @@ __global__ void k_tsqr_dep(const double *__restrict__ R, int64_t ldr, int kb, co
         dep[j] = bad;
     }
     __syncthreads();
-    // ||(R S^{-1})^{-1}||_F^2 with S = diag of R's column norms (the scaled factor
-    // has unit-norm columns, so its condition number is at most sqrt(kb) times
-    // that norm): thread j solves for column j by back-substitution
+    // ||(R S^{-1})^{-1}||_F^2 with S = diag of R's column norms (an upper bound
+    // of the squared 2-norm of the scaled factor's inverse): thread j solves for
+    // column j by back-substitution
     if (j < kb) {
         double f = 0.0;
         const double rjj = piv[j];
@@ -257,8 +257,9 @@ __global__ void k_tsqr_dep(const double *__restrict__ R, int64_t ldr, int kb, co
             f += fro[i];
         }
         dep[kb] = any;
-        // a second pass (projection, then TSQR again) unless kappa <= 100 is certain
-        dep[kb + 1] = rmin < 0.01 || !((double)kb * f <= 1e4);
+        // a second pass (projection, then TSQR again) unless the inverse of the
+        // scaled factor is certain to amplify components along V by at most 100
+        dep[kb + 1] = rmin < 0.01 || !(f <= 1e4);
     }
 }
 
