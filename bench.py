@@ -17,7 +17,9 @@ residual certificate is <= 1e-8) on the graph already resident in HBM; the
 graph build (host edge upload included) is timed separately and excluded.
 The roofline figure is the fused Chebyshev sparse step (k_cheb_step), timed
 live with HIP events on the solve's stream around every filter in the timed
-solves.  The CPU baseline is the FP64 oracle on a bounded sample of the same
+solves; beside it, nnz gathers of whole rows at uniformly random positions of a
+table the size of the gathered block (the step's neighbour reads with no
+locality at all).  The CPU baseline is the FP64 oracle on a bounded sample of the same
 workload (stated in the line), on the host's cores.
 
 Prints exactly one JSON line on stdout; progress goes to stderr.
@@ -137,6 +139,34 @@ def run_form(cd, torch, g, cfg, form, steps, warmup, seed, net=None):
     evals, evecs = r.evals.cpu().numpy(), r.evecs
     del ws
     return rec, evals, evecs
+
+
+def random_gather(cd, torch, n, nnz, row_bytes, t_launch):
+    """nnz gathers of whole rows at uniformly random positions of a table the size
+    of the gathered block (chebdav_probe_gather, the sparse step's load shape),
+    timed with events on the current stream: the time the step's neighbour reads
+    would take with no locality at all, beside the step's own time."""
+    if row_bytes not in (128, 256, 512):
+        return None
+    table = torch.empty(n * row_bytes, dtype=torch.uint8, device="cuda")
+    table.zero_()
+    cd.probe_gather(table, row_bytes, nnz, seed=1)
+    ts = []
+    for rep in range(3):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        done, _ = cd.probe_gather(table, row_bytes, nnz, seed=2 + rep)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    del table
+    torch.cuda.empty_cache()
+    t = sorted(ts)[1] * nnz / done  # median, scaled to exactly nnz gathers
+    log("random whole-row gathers (%d bytes, %d-row table): %.1f us for nnz = %d, %.2f G rows/s; "
+        "sparse step %.1f us" % (row_bytes, n, 1e6 * t, nnz, nnz / t / 1e9, 1e6 * t_launch))
+    return {"row_bytes": row_bytes, "table_bytes": n * row_bytes, "gathers": nnz, "us": 1e6 * t,
+            "rows_per_s": nnz / t, "step_over_gathers": t_launch / t}
 
 
 def measured_traffic(workload, kernel):
@@ -427,6 +457,7 @@ def main():
     achieved = bstep / t_launch / 1e9
     kname = step_kernel_name(n, kb, s)
     traffic = measured_traffic(args.workload, kname) if s == 8 else None
+    gather = random_gather(cd, torch, n, g.nnz, kb * s, t_launch)
     line = {
         "metric": METRIC,
         "value": prim["seconds"],
@@ -460,6 +491,7 @@ def main():
             "traffic_over_algorithmic": None if traffic is None else traffic / bstep,
             "gathered_block_bytes": n * kb * s,
             "block_fits_infinity_cache": n * kb * s <= INFINITY_CACHE_BYTES,
+            "random_gather": gather,
         },
         "iterations": prim["iterations"],
         "n_spmm_filter": prim["n_spmm_filter"],

@@ -432,6 +432,23 @@ chebdav_status chebdav_philox_fill(double *X, int64_t n, int w, int64_t ld, uint
  * then a round-to-nearest division.  deg, dinv: device arrays of n entries. */
 chebdav_status chebdav_dinv(const int32_t *deg, double *dinv, int64_t n, void *hip_stream);
 
+/* Measurement utility (not a step of the method): `gathers` reads of whole rows
+ * of `row_bytes` bytes (128, 256 or 512) at uniformly random row indices of
+ * `table` (device, rows x row_bytes, row-major, 16-byte aligned; the caller
+ * owns it and its contents do not matter), issued with the sparse step's load
+ * shape.  This is the access pattern of the sparse step (Alg. 3; Table 1's
+ * O(nnz m kb) filter term) on a graph without locality whose gathered block
+ * exceeds the caches, so the time of nnz such gathers over a table the size
+ * of the block bounds one step from below on the GPU at hand.  The kernel
+ * rounds `gathers` up to a multiple of its group count and stores that number
+ * in *performed (host, may be NULL); `out` (device) receives
+ * chebdav_probe_gather_out_len() doubles that keep the loads live.  Stream-
+ * ordered; the caller times the launch (events on hip_stream).  EINVAL for a
+ * NULL or misaligned pointer, rows < 1, gathers < 0 or another row size. */
+chebdav_status chebdav_probe_gather(const void *table, int64_t rows, int row_bytes, int64_t gathers,
+                                    uint64_t seed, double *out, int64_t *performed, void *hip_stream);
+int64_t chebdav_probe_gather_out_len(void);
+
 /* Message for the calling thread's most recent error (never NULL). */
 const char *chebdav_last_error(void);
 

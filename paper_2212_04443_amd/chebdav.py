@@ -41,6 +41,7 @@ EXPORTED = [
     "chebdav_cluster_workspace_size", "chebdav_cluster",
     "chebdav_lanczos_bounds_workspace_size", "chebdav_lanczos_bounds",
     "chebdav_tsqr_workspace_size", "chebdav_tsqr", "chebdav_filter_noalloc",
+    "chebdav_probe_gather", "chebdav_probe_gather_out_len",
 ]
 
 
@@ -130,6 +131,7 @@ def _load():
         "chebdav_cluster": [p, i64, i64, i32, i32, i32, u64, p, p, P(i32), P(d), p, sz, p],
         "chebdav_lanczos_bounds_workspace_size": [p, i32, P(sz)],
         "chebdav_lanczos_bounds": [p, i32, u64, P(d), P(d), P(d), P(d), P(i32), p, sz, p],
+        "chebdav_probe_gather": [p, i64, i32, i64, u64, p, P(i64), p],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -137,6 +139,8 @@ def _load():
         f.restype = ctypes.c_int
     L.chebdav_graph_free.argtypes = [p]
     L.chebdav_graph_free.restype = None
+    L.chebdav_probe_gather_out_len.argtypes = []
+    L.chebdav_probe_gather_out_len.restype = ctypes.c_int64
     L.chebdav_last_error.argtypes = []
     L.chebdav_last_error.restype = ctypes.c_char_p
     return L
@@ -222,6 +226,20 @@ def build_laplacian(edges, n_nodes: int, device="cuda", stream=None) -> Graph:
         _check(_lib.chebdav_build_laplacian(ptr, n_edges, int(n_nodes), on_dev, _stream(stream),
                                             ctypes.byref(h)))
     return Graph(h, torch.device(device))
+
+
+def probe_gather(table: torch.Tensor, row_bytes: int, gathers: int, seed: int = 0, stream=None):
+    """chebdav_probe_gather: `gathers` random whole-row reads of `row_bytes` bytes from
+    the rows of `table` (a device tensor of rows x row_bytes bytes, any dtype).
+    Returns (gathers performed, the device output that keeps the loads live)."""
+    nbytes = table.numel() * table.element_size()
+    if not table.is_contiguous() or nbytes % row_bytes:
+        raise ValueError("table must be contiguous and a whole number of rows")
+    out = torch.empty(int(_lib.chebdav_probe_gather_out_len()), dtype=torch.float64, device=table.device)
+    done = ctypes.c_int64()
+    _check(_lib.chebdav_probe_gather(_ptr(table), nbytes // row_bytes, row_bytes, gathers, seed, _ptr(out),
+                                     ctypes.byref(done), _stream(stream)))
+    return done.value, out
 
 
 def graph_row_split(g: Graph):

@@ -290,6 +290,13 @@ chebdav_status chebdav_philox_fill(double *X, int64_t n, int w, int64_t ld, uint
     return philox_fill(X, n, w, ld, seed, first_col, as_stream(hip_stream));
 }
 
+chebdav_status chebdav_probe_gather(const void *table, int64_t rows, int row_bytes, int64_t gathers,
+                                    uint64_t seed, double *out, int64_t *performed, void *hip_stream) {
+    return probe_gather(table, rows, row_bytes, gathers, seed, out, performed, as_stream(hip_stream));
+}
+
+int64_t chebdav_probe_gather_out_len(void) { return probe_gather_out_len(); }
+
 chebdav_status chebdav_dinv(const int32_t *deg, double *dinv, int64_t n, void *hip_stream) {
     if (n < 0 || (n > 0 && (!deg || !dinv))) return fail(CHEBDAV_EINVAL, "bad arguments");
     return dinv_table(deg, dinv, n, as_stream(hip_stream));

@@ -152,6 +152,10 @@ chebdav_status fill_f64(double *p, int64_t count, double v, hipStream_t st);
 chebdav_status philox_fill(double *X, int64_t n, int w, int64_t ld, uint64_t seed,
                            uint64_t first_col, hipStream_t st, const double *rs = nullptr);
 // flag[0] |= any non-finite entry in X (n x w, ld).
+// Random whole-row gathers (measurement utility); `out` holds probe_gather_out_len() doubles.
+chebdav_status probe_gather(const void *table, int64_t rows, int row_bytes, int64_t gathers, uint64_t seed,
+                            double *out, int64_t *performed, hipStream_t st);
+int64_t probe_gather_out_len();
 chebdav_status check_finite(const double *X, int64_t ld, int w, int64_t n, int *flag,
                             hipStream_t st);
 
