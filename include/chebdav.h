@@ -228,12 +228,19 @@ typedef struct {
     double lowb;            /* spectrum lower bound (filter scale point), normally 0       */
     double low_nwb0;        /* first cut; NaN or <= lowb -> lowb + (upperb - lowb) k_want / n */
     chebdav_dtype filter_dtype;  /* F64, or F32 for the mixed-precision form              */
-    double f32_switch_tol;  /* F32 form: the filter runs in FP64 once the smallest residual
-                               among the non-converged leading pairs falls below this
-                               (0 -> 3e-7, about five FP32 unit roundoffs), or after two
-                               FP32 iterations in a row that neither locked a pair nor
-                               halved that residual nor halved the largest open residual
-                               among the wanted pairs; every other step is always FP64    */
+    double f32_switch_tol;  /* F32 form: the residual floor of FP32 filtering (0 -> 3e-7,
+                               about five FP32 unit roundoffs).  The filter runs in FP64
+                               from the first iteration after which (a) when the kb
+                               evaluated pairs hold every open wanted pair and the largest
+                               of their residuals is at most a tenth of the distance from
+                               the last wanted Ritz value theta to the next cut: one more
+                               FP32 iteration, which divides residuals by
+                               |C_m((theta - c)/e)| but not below this floor, would not
+                               lower the predicted number of FP64 iterations; (b) otherwise:
+                               the smallest open residual is below this floor; (c) in any
+                               case: two FP32 iterations in a row neither locked a pair
+                               nor halved the smallest open residual nor the largest
+                               wanted open residual.  Every other step is always FP64   */
     uint64_t seed;          /* Philox key for all random vectors                           */
     int timing;             /* nonzero: time the filter with HIP events (stats fields)     */
     chebdav_orth orth;      /* orthonormalization of new blocks (default CHOLQR)           */

@@ -407,6 +407,9 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
         rec.max_residual = 0.0;
         double max_open_res = 0.0;  // largest open residual among the wanted pairs
         const int n_wanted = std::min(nres, r.k_want - kc);
+        // Ritz value of the last wanted pair, when the kb evaluated pairs hold every
+        // wanted pair not yet locked (else NaN)
+        const double theta_last = (r.k_want - kc <= nres && n_wanted > 0) ? D[n_wanted - 1] : NAN;
         for (int i = 0; i < nres; ++i) {
             if (!(res[i] <= r.tol)) min_open_res = std::min(min_open_res, res[i]);
             if (!(res[i] <= r.tol) && i < n_wanted) max_open_res = std::max(max_open_res, res[i]);
@@ -538,12 +541,21 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             const double med = median_of(std::vector<double>(Dact.begin(), Dact.begin() + kact));
             if (lowb < med && med < upperb) low_nwb = med;
         }
-        // mixed precision: FP64 filtering once the leading open residual is small,
-        // or once FP32 filtering stops making progress on the whole wanted block
-        // (two iterations in a row that neither locked a pair nor halved the
-        // smallest open residual nor the largest open residual among the wanted
-        // pairs: a leading pair held at its FP32 floor does not stop the FP32
-        // filter while the rest of the block still converges at half the bytes)
+        // mixed precision: when to filter in FP64 from now on.
+        // (a) When the evaluated block holds every wanted pair still open and their
+        //     Ritz pairs are accurate enough to predict the filter's effect (the
+        //     largest wanted residual is at most a tenth of the distance from the
+        //     last wanted Ritz value theta up to the next cut, so the eigenvalue it
+        //     approximates is that far below the cut too): per FP64 iteration the
+        //     filter of Alg. 3 divides that pair's residual by about
+        //     |C_m((theta - c) / e)| (unwanted components stay below 1 in size),
+        //     while one more FP32 iteration does the same but stops at the FP32
+        //     floor f32_switch_tol.  Switch as soon as one more FP32 iteration would
+        //     not save an FP64 iteration.
+        // (b) Otherwise once the smallest open residual reaches that floor.
+        // (c) Either way once FP32 filtering stops making progress on the wanted
+        //     block: two iterations in a row that neither locked a pair nor halved
+        //     the smallest open residual nor the largest wanted open residual.
         if (!use_f64_filter) {
             if (ec > 0 || min_open_res < 0.5 * f32_best || max_open_res < 0.5 * f32_best_max) {
                 f32_stall = 0;
@@ -552,7 +564,19 @@ chebdav_status solve(const Graph *g, const chebdav_params *p, const double *V_in
             }
             f32_best = std::min(f32_best, min_open_res);
             f32_best_max = std::min(f32_best_max, max_open_res);
-            if (min_open_res < r.f32_switch_tol || f32_stall >= 2) use_f64_filter = true;
+            bool to_f64;
+            if (theta_last < low_nwb && max_open_res <= 0.1 * (low_nwb - theta_last)) {
+                const double c = 0.5 * (low_nwb + upperb), e = 0.5 * (upperb - low_nwb);
+                const double gain = std::cosh(r.m * std::acosh((c - theta_last) / e));  // |C_m| > 1
+                auto fp64_its = [&](double res0) {
+                    if (res0 <= r.tol) return 0.0;
+                    return std::max(1.0, std::ceil(std::log(res0 / r.tol) / std::log(gain)));
+                };
+                to_f64 = fp64_its(max_open_res) <= fp64_its(std::max(max_open_res / gain, r.f32_switch_tol));
+            } else {
+                to_f64 = min_open_res < r.f32_switch_tol;
+            }
+            if (to_f64 || f32_stall >= 2) use_f64_filter = true;
         }
         if (r.log_cb) r.log_cb(&rec, r.log_user);
     }
