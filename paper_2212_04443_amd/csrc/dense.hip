@@ -38,11 +38,14 @@ __device__ inline d4_t mfma16x16x4(double a, double b, d4_t c) {
 // segments per load).  The loads of the next trip are issued before the MFMAs
 // of the current one (two register sets), so a wavefront always has a trip of
 // loads in flight.  TP = 2 serves p <= 32 without idle matrix-core work.
-template <int TP, int TQT, int UR>
-__global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy, int q,
-                                             int64_t n, int64_t rows_per_split, double *__restrict__ part) {
+// NWG wavefronts may share a split (trips interleaved between them; their tiles
+// are added in wavefront order through LDS before the one store): more loads
+// in flight when short blocks leave fewer splits than wavefronts the GPU holds.
+template <int TP, int TQT, int UR, int NWG = 1>
+__global__ void __launch_bounds__(64 * NWG) k_gram(Seg2 xs, const double *__restrict__ Y, int64_t ldy, int q,
+                                                   int64_t n, int64_t rows_per_split, double *__restrict__ part) {
     const int p = xs.cols();
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kr = lane >> 4, cc = lane & 15;
     const int i0 = blockIdx.x * (16 * TP), j0 = blockIdx.y * (16 * TQT);
     const int64_t r_beg = (int64_t)blockIdx.z * rows_per_split;
@@ -76,19 +79,39 @@ __global__ void __launch_bounds__(64) k_gram(Seg2 xs, const double *__restrict__
 #pragma unroll
                 for (int u = 0; u < TQT; ++u) acc[t][u] = mfma16x16x4(a[h][t], b[h][u], acc[t][u]);
     };
-    constexpr int64_t step = 4 * UR;
+    constexpr int64_t step = 4 * UR, stride = step * NWG;
     double a0[UR][TP], b0[UR][TQT], a1[UR][TP], b1[UR][TQT];
-    int64_t r = r_beg;
+    int64_t r = r_beg + wave * step;
     if (r < r_end) load(r, a0, b0);
     while (r < r_end) {
-        const int64_t r1 = r + step;
+        const int64_t r1 = r + stride;
         if (r1 < r_end) load(r1, a1, b1);
         trip(a0, b0);
         if (r1 >= r_end) break;
-        const int64_t r2 = r1 + step;
+        const int64_t r2 = r1 + stride;
         if (r2 < r_end) load(r2, a0, b0);
         trip(a1, b1);
         r = r2;
+    }
+    if constexpr (NWG > 1) {
+        __shared__ d4_t red[TP * TQT][64];
+        for (int w = 1; w < NWG; ++w) {
+            if (wave == w) {
+#pragma unroll
+                for (int t = 0; t < TP; ++t)
+#pragma unroll
+                    for (int u = 0; u < TQT; ++u) red[t * TQT + u][lane] = acc[t][u];
+            }
+            __syncthreads();
+            if (wave == 0) {
+#pragma unroll
+                for (int t = 0; t < TP; ++t)
+#pragma unroll
+                    for (int u = 0; u < TQT; ++u) acc[t][u] += red[t * TQT + u][lane];
+            }
+            __syncthreads();
+        }
+        if (wave != 0) return;
     }
     double *out = part + (int64_t)blockIdx.z * p * q;
 #pragma unroll
@@ -412,16 +435,26 @@ chebdav_status gram(const Seg2 &Xs, const double *Y, int64_t ldy, int q, int64_t
     const int qt = std::min(q, TB);
     const int pt = p <= 32 ? 32 : TB;  // X tile: 32 or 64 columns
     const dim3 grid((unsigned)ceil_div(p, pt), (unsigned)ceil_div(q, qt), (unsigned)splits);
+    // one tile and fewer row splits than the 2048 wanted (short blocks): two
+    // wavefronts per split where measured faster (tiles of at most 64 x 32 or
+    // 32 x 64: 20-25 % at 200k rows; 64 x 64 tiles lose)
+    const bool pair = grid.x * grid.y == 1 && splits < 2048;
     if (pt == 32) {
         if (qt <= 16)
             hipLaunchKernelGGL((k_gram<2, 1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else if (qt <= 32 && pair)
+            hipLaunchKernelGGL((k_gram<2, 2, 4, 2>), grid, dim3(128), 0, st, Xs, Y, ldy, q, n, rps, partial);
         else if (qt <= 32)
             hipLaunchKernelGGL((k_gram<2, 2, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else if (pair)
+            hipLaunchKernelGGL((k_gram<2, 4, 2, 2>), grid, dim3(128), 0, st, Xs, Y, ldy, q, n, rps, partial);
         else
             hipLaunchKernelGGL((k_gram<2, 4, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
     } else {
         if (qt <= 16)
             hipLaunchKernelGGL((k_gram<4, 1, 4>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
+        else if (qt <= 32 && pair)
+            hipLaunchKernelGGL((k_gram<4, 2, 2, 2>), grid, dim3(128), 0, st, Xs, Y, ldy, q, n, rps, partial);
         else if (qt <= 32)
             hipLaunchKernelGGL((k_gram<4, 2, 2>), grid, dim3(64), 0, st, Xs, Y, ldy, q, n, rps, partial);
         else

@@ -28,17 +28,20 @@ constexpr int kMaxKb = 64;
 // R^{-1} comes from Gauss-Jordan elimination on [R | I] from the last row up.
 constexpr int kCholP = 16;  // thread grid edge: kCholP^2 threads
 
+// TT x TT entries per thread: kb <= 16 TT (TT = 2 up to kb = 32, so the
+// per-step loops carry no tiles that are wholly out of range).
+template <int TT>
 __global__ void __launch_bounds__(kCholP * kCholP) k_chol_rinv(const double *__restrict__ G, int kb,
                                                    const double *__restrict__ norm0,
                                                    double *__restrict__ Rinv, int *__restrict__ dep,
                                                    int scaled) {
-    constexpr int P = kCholP, TT = kMaxKb / P, NT = P * P;
+    constexpr int P = kCholP, NT = P * P, KM = P * TT;
     // R in the upper triangle of A; B = R^{-1} (upper) kept transposed in the
     // strict lower triangle of A, its diagonal in bd
-    __shared__ double A[kMaxKb][kMaxKb + 1];
-    __shared__ double bd[kMaxKb], dR[kMaxKb];  // diagonals of R^{-1} and of R
-    __shared__ double s[kMaxKb];
-    __shared__ int d[kMaxKb + 2];
+    __shared__ double A[KM][KM + 1];
+    __shared__ double bd[KM], dR[KM];  // diagonals of R^{-1} and of R
+    __shared__ double s[KM];
+    __shared__ int d[KM + 2];
     const int tid = threadIdx.x, ti = tid / P, tj = tid % P;
     if (tid < kb) {
         d[tid] = 0;
@@ -234,7 +237,11 @@ __global__ void __launch_bounds__(256) k_small_gemm(const double *__restrict__ A
 chebdav_status chol_rinv(const double *G, int kb, const double *norm0, double *Rinv, int *dep,
                          int scaled, hipStream_t st) {
     if (kb < 1 || kb > kMaxKb) return fail(CHEBDAV_EUNSUPPORTED, "block size %d outside [1, %d]", kb, kMaxKb);
-    hipLaunchKernelGGL(k_chol_rinv, dim3(1), dim3(kCholP * kCholP), 0, st, G, kb, norm0, Rinv, dep, scaled);
+    if (kb <= 2 * kCholP)
+        hipLaunchKernelGGL(k_chol_rinv<2>, dim3(1), dim3(kCholP * kCholP), 0, st, G, kb, norm0, Rinv, dep, scaled);
+    else
+        hipLaunchKernelGGL(k_chol_rinv<kMaxKb / kCholP>, dim3(1), dim3(kCholP * kCholP), 0, st, G, kb, norm0, Rinv,
+                           dep, scaled);
     CD_LAUNCH_CHECK();
     return CHEBDAV_OK;
 }

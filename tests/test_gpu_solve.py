@@ -355,13 +355,25 @@ def test_chung_lu_500k_oracle_parity(cd, oracle_mod, dev):
     gap after the 32nd eigenvalue is only 2.3e-3 (the oracle's 36 smallest:
     0.234955 then 0.237232), so Davis-Kahan bounds each solution's angle to the
     exact subspace by sqrt(32) 1e-8 / 2.3e-3 = 2.5e-5, and the two solutions'
-    largest principal angle by twice that."""
+    largest principal angle by twice that.  The FP32-filter form (its switch to
+    FP64 predicted from the Chebyshev rate at the last wanted Ritz value) is held
+    to the same bar against the same oracle solve."""
     e, n = synth.chung_lu(500_000, seed=synth.graphs.DEFAULT_SEED + 4)
     print("case chung-lu 500k full solve (n=%d)" % n, flush=True)
     ev, V, st, ref = _parity(cd, oracle_mod, e, n, 32, 32, 20, seed=1)
     ang = sin_max_angle(ref.evecs, V)
     print("chung-lu 500k: largest principal angle %.3g" % ang)
     assert ang <= 1e-4
+    print("case chung-lu 500k FP32 form", flush=True)
+    _, ev32, V32, st32 = _gpu_solve(cd, e, n, k_want=32, kb=32, m=20, seed=1, filter_dtype=cd.F32)
+    res32 = _fresh_residuals(oracle_mod, ev32, V32)
+    print("chung-lu 500k FP32 form: %d iterations (FP32 steps %d of %d), max res %.3g, max dlam %.3g"
+          % (st32["iterations"], st32["n_spmm_filter_f32"], st32["n_spmm_filter"], res32.max(),
+             np.abs(ev32 - ref.evals).max()))
+    assert res32.max() <= 1e-8 and st32["converged"] >= 32
+    assert np.abs(ev32 - ref.evals).max() <= 1e-10
+    assert sin_max_angle(ref.evecs, V32) <= 1e-4
+    assert 0 < st32["n_spmm_filter_f32"] < st32["n_spmm_filter"]
 
 
 def test_f32_form_stall_guard(cd, oracle_mod, dev):
