@@ -177,6 +177,34 @@ def _ld(t: torch.Tensor) -> int:
     return t.stride(0)
 
 
+def _block(t, name: str, rows: int, dtypes, cols: int | None = None, device=None):
+    """Checks a device block before its pointer crosses the ABI: 2-D, `rows` rows
+    with contiguous rows (leading dimension >= width), one of `dtypes`, on the
+    CUDA device (`device` if given), `cols` columns if given.  The library reads
+    and writes through raw pointers, so a wrong shape would run off the buffer."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    if t.dim() != 2 or t.stride(1) != 1 or t.stride(0) < t.shape[1]:
+        raise ValueError("%s must be 2-D with contiguous rows" % name)
+    if t.shape[0] != rows:
+        raise ValueError("%s has %d rows, expected %d" % (name, t.shape[0], rows))
+    if cols is not None and t.shape[1] != cols:
+        raise ValueError("%s has %d columns, expected %d" % (name, t.shape[1], cols))
+    if t.dtype not in dtypes:
+        raise ValueError("%s must be %s" % (name, " or ".join(str(d) for d in dtypes)))
+    if device is not None and not _same_device(t.device, device):
+        raise ValueError("%s is on %s, expected %s" % (name, t.device, device))
+    return t
+
+
+def _same_device(a, b) -> bool:
+    da, db = torch.device(a), torch.device(b)
+    if da.type != db.type:
+        return False
+    cur = torch.cuda.current_device() if da.type == "cuda" else 0
+    return (da.index if da.index is not None else cur) == (db.index if db.index is not None else cur)
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
@@ -263,6 +291,10 @@ def graph_export(g: Graph, stream=None):
 def spmm(g: Graph, alpha: float, beta: float, gamma: float, U: torch.Tensor, Z, Y: torch.Tensor,
          stream=None):
     """Y = alpha D^{-1/2} S D^{-1/2} U + beta U + gamma Z (float64 or float32)."""
+    _block(U, "U", g.n, (torch.float64, torch.float32), device=g.device)
+    _block(Y, "Y", g.n, (U.dtype,), U.shape[1], g.device)
+    if Z is not None:
+        _block(Z, "Z", g.n, (U.dtype,), U.shape[1], g.device)
     dt = {torch.float64: F64, torch.float32: F32}[U.dtype]
     ld = _ld(U)
     if _ld(Y) != ld or (Z is not None and _ld(Z) != ld):
@@ -276,9 +308,11 @@ def filter(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float = 2.0, sc
            dtype: int = F64, Y: torch.Tensor | None = None, workspace: torch.Tensor | None = None,
            stream=None) -> torch.Tensor:
     """chebdav_filter: Y = p_m(A) X (X float64, n x kb)."""
+    _block(X, "X", g.n, (torch.float64,), device=g.device)
     kb = X.shape[1]
     if Y is None:
         Y = torch.empty_like(X)
+    _block(Y, "Y", g.n, (torch.float64,), kb, g.device)
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_filter_workspace_size(g.handle, kb, dtype, ctypes.byref(nb)))
     if workspace is None or workspace.numel() < nb.value:
@@ -292,9 +326,11 @@ def filter_noalloc(g: Graph, X: torch.Tensor, m: int, cut: float, upper: float =
                    dtype: int = F64, Y: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     """chebdav_filter_noalloc: chebdav_filter on the library's static scratch
     (no workspace; Y must be given by callers that cannot allocate)."""
+    _block(X, "X", g.n, (torch.float64,), device=g.device)
     kb = X.shape[1]
     if Y is None:
         Y = torch.empty_like(X)
+    _block(Y, "Y", g.n, (torch.float64,), kb, g.device)
     _check(_lib.chebdav_filter_noalloc(g.handle, _ptr(X), _ld(X), _ptr(Y), _ld(Y), kb, m, cut, upper, scale_pt,
                                        dtype, _stream(stream)))
     return Y
@@ -304,8 +340,11 @@ def orthonormalize(V, X: torch.Tensor, seed: int = 0, first_random_col: int = 0,
                    stream=None) -> int:
     """chebdav_orthonormalize, in place on X; returns the number of replaced columns.
     method: "cholqr" (Cholesky QR twice) or "tsqr" (Householder TSQR)."""
+    _block(X, "X", X.shape[0] if X.dim() == 2 else -1, (torch.float64,))
     n, kb = X.shape
     ksub = 0 if V is None else V.shape[1]
+    if ksub:
+        _block(V, "V", n, (torch.float64,), device=X.device)
     meth = _ORTH[method]
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_orthonormalize_workspace_size(n, ksub, kb, meth, ctypes.byref(nb)))
@@ -320,9 +359,11 @@ def orthonormalize(V, X: torch.Tensor, seed: int = 0, first_random_col: int = 0,
 def tsqr(X: torch.Tensor, Q: torch.Tensor | None = None, stream=None):
     """chebdav_tsqr: X = Q R (thin QR, R with a non-negative diagonal).  Q may be X
     itself (in place).  Returns (Q, R)."""
+    _block(X, "X", X.shape[0] if X.dim() == 2 else -1, (torch.float64,))
     n, kb = X.shape
     if Q is None:
         Q = torch.empty((n, kb), dtype=torch.float64, device=X.device)
+    _block(Q, "Q", n, (torch.float64,), kb, X.device)
     R = torch.empty((kb, kb), dtype=torch.float64, device=X.device)
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_tsqr_workspace_size(n, kb, ctypes.byref(nb)))
@@ -376,7 +417,8 @@ def solve(g: Graph, params: Params, V_init: torch.Tensor | None = None,
     k_init = 0
     vptr = ctypes.c_void_p(0)
     if V_init is not None:
-        if not V_init.is_contiguous() or V_init.dtype != torch.float64:
+        _block(V_init, "V_init", g.n, (torch.float64,), device=g.device)
+        if not V_init.is_contiguous():
             raise ValueError("V_init must be a contiguous float64 (n, k_init) tensor")
         k_init = V_init.shape[1]
         vptr = _ptr(V_init)
@@ -424,6 +466,14 @@ def _ptr_array(ts):
     return (ctypes.c_void_p * 3)(*[t.data_ptr() for t in ts])
 
 
+def _gcn_args(g: Graph, dims, X0, W):
+    _block(X0, "X0", g.n, (torch.float32,), dims[0], g.device)
+    for l in range(3):
+        _block(W[l], "W[%d]" % l, dims[l], (torch.float32,), dims[l + 1], g.device)
+        if not W[l].is_contiguous():
+            raise ValueError("W[%d] must be contiguous" % l)
+
+
 def gcn_workspace(g: Graph, dims) -> torch.Tensor:
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_gcn_workspace_size(g.handle, _dims(dims), ctypes.byref(nb)))
@@ -433,6 +483,7 @@ def gcn_workspace(g: Graph, dims) -> torch.Tensor:
 def gcn_forward(g: Graph, dims, X0: torch.Tensor, W, acts=None, out=None, workspace=None, stream=None):
     """chebdav_gcn_forward.  W: three float32 tensors (d_l x d_{l+1}).  Returns (out, acts)."""
     n = g.n
+    _gcn_args(g, dims, X0, W)
     if acts is None:
         acts = torch.empty(n * (dims[1] + dims[2]), dtype=torch.float32, device=g.device)
     if out is None:
@@ -445,6 +496,10 @@ def gcn_forward(g: Graph, dims, X0: torch.Tensor, W, acts=None, out=None, worksp
 
 def gcn_backward(g: Graph, dims, X0, W, acts, d_out, dW=None, workspace=None, stream=None):
     """chebdav_gcn_backward.  Returns the three weight gradients."""
+    _gcn_args(g, dims, X0, W)
+    _block(d_out, "d_out", g.n, (torch.float32,), dims[3], g.device)
+    if not acts.is_cuda or acts.dtype != torch.float32 or acts.numel() < g.n * (dims[1] + dims[2]):
+        raise ValueError("acts must be the float32 activations of gcn_forward")
     if dW is None:
         dW = [torch.empty_like(w) for w in W]
     ws = workspace if workspace is not None else gcn_workspace(g, dims)
@@ -461,6 +516,8 @@ def gcn_features(g: Graph, seed: int, n_gauss: int = 16, stream=None) -> torch.T
 
 def subspace_loss(X: torch.Tensor, U: torch.Tensor, grad: bool = True, workspace=None, stream=None):
     """chebdav_subspace_loss: (loss, dL/dX or None)."""
+    _block(X, "X", X.shape[0] if X.dim() == 2 else -1, (torch.float32,))
+    _block(U, "U", X.shape[0], (torch.float64,), device=X.device)
     n, kx = X.shape
     ku = U.shape[1]
     nb = ctypes.c_size_t()
@@ -480,6 +537,7 @@ def adam_step(params, grads, m, v, lr, beta1=0.9, beta2=0.999, eps=1e-8, step=1,
 
 def rayleigh_ritz(g: Graph, X: torch.Tensor, seed: int = 0, stream=None):
     """chebdav_rayleigh_ritz: (V float64 n x k, ritz values ascending)."""
+    _block(X, "X", g.n, (torch.float32,), device=g.device)
     n, k = X.shape
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_rayleigh_ritz_workspace_size(g.handle, k, ctypes.byref(nb)))
@@ -495,6 +553,7 @@ def cluster(U: torch.Tensor, n_clusters: int, seed: int = 0, max_iter: int = 100
     """chebdav_cluster: row normalization of the eigenvector block U (float64,
     n x k) and K-means.  Returns (labels int32[n], centres n_clusters x k, rounds,
     inertia)."""
+    _block(U, "U", U.shape[0] if U.dim() == 2 else -1, (torch.float64,))
     n, k = U.shape
     nb = ctypes.c_size_t()
     _check(_lib.chebdav_cluster_workspace_size(n, k, n_clusters, ctypes.byref(nb)))
