@@ -1,6 +1,6 @@
 """Oracle (test infrastructure): the clustering tail of spectral clustering
 (Alg. 1, steps 3 and 4) in plain FP64 NumPy, and the two agreement scores used
-to judge a partition against the planted blocks.
+to score a partition against the planted blocks.
 
 Readings (the paper names K-means and row normalization only):
   * a row is divided by its 2-norm (the plain definition; no summation order
